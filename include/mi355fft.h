@@ -1,0 +1,224 @@
+/*
+ * mi355fft - complex Cooley-Tukey FFT for AMD MI355X (gfx950), C ABI.
+ *
+ * Operation (Zhang, Hu, Yin, Hu, "A GPU Based Memory Optimized Parallel
+ * Method For FFT Implementation", Sec. 2.1):
+ *   forward, eq. 1:  X(k) = sum_{n<N} x(n) W_N^{nk},        W_N = exp(-2*pi*i/N)
+ *   inverse, eq. 2:  x(n) = (1/N) sum_{k<N} X(k) W_N^{-nk}
+ * The forward transform is unscaled and the inverse carries 1/N unless
+ * fft_set_scale() overrides it.  2-D transforms apply eq. 1 / eq. 2 along
+ * every row and then every column (Sec. 2.3.2); the default inverse scale is
+ * then 1/(rows*cols).
+ *
+ * Method (Sec. 2.3): a transform that fits one workgroup runs all of its
+ * butterfly stages in LDS and registers in one kernel.  Longer transforms
+ * are split in global memory as N = N1*N2 (the reducibility of eq. 5) into
+ * a pass of N1-point sub-transforms, a twiddle multiply W_N^{n2*k1}, and a
+ * pass of N2-point sub-transforms; each pass is one kernel.  Twiddle factors
+ * come from sin/cos tables computed once per plan (Sec. 2.3.1).
+ *
+ * Data layout: complex values interleaved (re, im), row-major, batch
+ * outermost, contiguous, natural order in and out.
+ *   FFT_C64   - float32 pairs (8 bytes per point)
+ *   FFT_C16F  - IEEE binary16 pairs (4 bytes per point)
+ *   FFT_C16BF - bfloat16 pairs (4 bytes per point)
+ * 16-bit data are converted to float32 on load and rounded to nearest even
+ * on store; all arithmetic and twiddles are float32.  Twiddle tables are
+ * computed in float64 and rounded to float32.
+ *
+ * Pointers: `in` and `out` are device pointers the caller owns; they must
+ * stay valid until the work queued on `stream` has finished.  `stream` is a
+ * hipStream_t passed as void* (NULL = the null stream).
+ *
+ * Errors: every call returns FFT_OK (0) or a negative FFT_ERR_* code; no
+ * C++ exception crosses this interface and nothing aborts.  Faults inside a
+ * kernel surface, as usual for HIP, at the caller's next synchronisation.
+ */
+#ifndef MI355FFT_H
+#define MI355FFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fft_plan_s *fft_plan_t;
+
+/* dtype */
+#define FFT_C64 0
+#define FFT_C16F 1
+#define FFT_C16BF 2
+
+/* direction: sign of the exponent of W (eq. 1 uses -1, eq. 2 uses +1) */
+#define FFT_FORWARD (-1)
+#define FFT_INVERSE (+1)
+
+/* status codes */
+#define FFT_OK 0
+#define FFT_ERR_INVALID_ARGUMENT (-1) /* null pointer, dims, batch, dtype, direction, schedule */
+#define FFT_ERR_UNSUPPORTED_SIZE (-2) /* a length that is not a power of two, or out of range */
+#define FFT_ERR_ALIGNMENT (-3)        /* in/out not aligned to the element size */
+#define FFT_ERR_INPLACE (-4)          /* in == out on a multi-pass plan with no workspace */
+#define FFT_ERR_HIP (-5)              /* a HIP call failed; see fft_last_hip_error() */
+#define FFT_ERR_NO_MEMORY (-6)        /* host or device allocation failed */
+#define FFT_ERR_WATCHDOG (-7)         /* the batched kernel's bounded wait expired */
+
+/* Size limits.  1-D lengths 1 .. 2^24; 2-D extents 1 .. 2^14 each. */
+#define FFT_MAX_LOG2_1D 24
+#define FFT_MAX_LOG2_2D 14
+
+/*
+ * Create a plan for `batch` transforms of shape n[0..dims) (dims 1 or 2;
+ * for dims 2, n[0] = rows, n[1] = columns, row-major), element type `dtype`
+ * and `direction`.  Builds the twiddle tables (float64 -> float32 on the
+ * host; generated on the GPU in float64 for 1-D lengths >= 2^22) and
+ * uploads them to the current device.  Blocking; not for use under stream
+ * capture.  On success *out holds the plan; on failure *out is NULL.
+ */
+int fft_plan(const int64_t *n, int64_t batch, int dims, int dtype, int direction,
+             fft_plan_t *out);
+
+/*
+ * As fft_plan, with an explicit schedule string (used by the autotuner and
+ * by tests).  NULL or "" selects the built-in choice.  Grammar:
+ *   schedule := item (';' item)*
+ *   item     := 'split=' N1            (1-D two-pass: first-pass length)
+ *             | 'a=' variant | 'b=' variant | 'row=' variant | 'col=' variant
+ *             | 'single=' variant
+ *   variant  := name as listed by fft_variant_name()
+ * FFT_ERR_INVALID_ARGUMENT if the string does not parse or names a variant
+ * that cannot run this size.
+ */
+int fft_plan_ex(const int64_t *n, int64_t batch, int dims, int dtype, int direction,
+                const char *schedule, fft_plan_t *out);
+
+/*
+ * Plan `count` independent 1-D transforms whose lengths sizes[0..count) are
+ * powers of two in 1 .. 2^24, packed back to back in the given order (the
+ * offset of transform i is the sum of sizes[0..i)).  fft_exec runs them all
+ * in ONE persistent kernel launch that takes work items from a device queue;
+ * a second-pass item of a two-pass transform waits on that transform's
+ * completion counter.  The queue state lives in the plan's workspace and is
+ * reset by the kernel itself, so the launch can be captured in a hipGraph
+ * and replayed.  Two fft_exec calls that share one workspace must not run
+ * concurrently.
+ */
+int fft_plan_many(const int64_t *sizes, int64_t count, int dtype, int direction,
+                  fft_plan_t *out);
+
+/*
+ * As fft_plan_many with a schedule string of ';'-separated items:
+ *   'p=' 8|16          points per lane (radix of the in-register stages)
+ *   'threads=' 256|512 workgroup size (not every dtype has every size)
+ *   'pass2=' t         lengths of at least 2^t use two passes (1 <= t <= 13)
+ *   'order=' bigfirst|given   order of the work queue
+ * FFT_ERR_INVALID_ARGUMENT for a malformed item or an uncompiled combination.
+ * In-place exec (in == out) is refused with FFT_ERR_INPLACE when any length
+ * uses two passes.
+ */
+int fft_plan_many_ex(const int64_t *sizes, int64_t count, int dtype, int direction,
+                     const char *schedule, fft_plan_t *out);
+
+/*
+ * Batched plans only: the second-pass tiles wait on a counter with a bounded
+ * spin.  fft_many_watchdog() reads (blocking) the flag the kernel sets when a
+ * wait expired, returning FFT_ERR_WATCHDOG if set (and clearing it if
+ * `clear`); fft_many_set_spin_limit() sets the bound (in sleep-polls,
+ * default 2^26).  An expired wait means the results are invalid.
+ */
+int fft_many_watchdog(fft_plan_t plan, int clear);
+int fft_many_set_spin_limit(fft_plan_t plan, int32_t limit);
+
+/*
+ * Queue the transform on `stream`.  Asynchronous: no host synchronisation, no
+ * allocation, no host reads of device data, so it may be captured into a
+ * hipGraph.  `in` and `out` must not partially overlap; in == out is allowed
+ * for one-pass plans, and for multi-pass plans once a workspace of
+ * fft_workspace_size() bytes is set (else FFT_ERR_INPLACE).  Input data are
+ * not modified unless in == out.
+ */
+int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
+
+/*
+ * Scale applied to every output value (default 1 forward, 1/(product of
+ * lengths) inverse, per transform for plan_many).  The adjoint of the forward
+ * transform is the inverse-direction plan with scale 1.
+ */
+int fft_set_scale(fft_plan_t plan, double scale);
+
+/*
+ * Device scratch a plan needs to run in place (1-D two-pass) or, for
+ * plan_many, for its queue and counters.  fft_set_workspace hands the plan
+ * caller-owned device memory of at least that many bytes (NULL, 0 returns to
+ * the plan-owned default, if any); the caller keeps it alive while the plan
+ * may run.
+ */
+int fft_workspace_size(fft_plan_t plan, size_t *bytes);
+int fft_set_workspace(fft_plan_t plan, void *ptr, size_t bytes);
+
+typedef struct {
+  int64_t n[2];          /* shape (n[1] = 1 for 1-D) */
+  int64_t batch;         /* transforms per exec (count for plan_many) */
+  int dims, dtype, direction;
+  int passes;            /* kernel launches per exec */
+  int64_t split[2];      /* 1-D two-pass: N1, N2 (0 otherwise) */
+  char pass_variant[4][32]; /* variant name of each launch */
+  int64_t points;        /* complex points per exec */
+  double flops;          /* nominal 5 N log2 N summed over transforms */
+  double bytes_min;      /* bytes read + written once (in + out) */
+  double bytes_pass[4];  /* algorithmic bytes read + written by each launch */
+  int gpu_twiddles;      /* 1 if the tables were generated on the GPU */
+} fft_plan_info_t;
+
+int fft_plan_info(fft_plan_t plan, fft_plan_info_t *info);
+
+/* Free the plan's tables and workspace.  NULL is a no-op. */
+int fft_destroy(fft_plan_t plan);
+
+/* Static text for a status code. */
+const char *fft_error_string(int status);
+
+/* The hipError_t of the last failing HIP call in this thread (0 if none). */
+int fft_last_hip_error(void);
+
+/*
+ * Kernel variants compiled into the library: fft_variant_count() of them;
+ * fft_variant_name(i) gives the i-th name (NULL if out of range) and
+ * fft_variant_describe(i, ...) its sub-transform length L, points per lane
+ * P, transforms per workgroup W, workgroup size and role (0 contiguous rows,
+ * 1 first pass of a split, 2 strided columns).
+ */
+int fft_variant_count(void);
+const char *fft_variant_name(int index);
+int fft_variant_describe(int index, int *L, int *P, int *W, int *threads, int *role,
+                         int *dtype);
+
+/*
+ * Host-only planning: the schedule fft_plan would choose, without touching
+ * the GPU.  Writes the pass count and up to 4 variant names (as in
+ * fft_plan_info_t.pass_variant) and the split.
+ */
+int fft_describe(const int64_t *n, int64_t batch, int dims, int dtype,
+                 const char *schedule, int *passes, char names[4][32],
+                 int64_t split[2]);
+
+/*
+ * Per-launch timing with HIP events recorded on the exec stream around each
+ * kernel.  fft_profile_enable(plan, 1) creates the events (blocking) and
+ * clears the totals; afterwards every fft_exec records them.  After the
+ * caller has synchronised the stream, fft_profile_collect() adds the elapsed
+ * time of the last exec's launches to running totals, and
+ * fft_profile_read(plan, pass, &ms, &count) returns the total milliseconds
+ * and the number of launches of pass `pass`.
+ */
+int fft_profile_enable(fft_plan_t plan, int enable);
+int fft_profile_collect(fft_plan_t plan);
+int fft_profile_read(fft_plan_t plan, int pass, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MI355FFT_H */

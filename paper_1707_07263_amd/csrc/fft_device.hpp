@@ -1,0 +1,355 @@
+// Device side of the MI355X FFT: complex helpers, in-register DFT codelets,
+// the LDS-exchange Stockham engine and the strip-pass kernel template.
+//
+// The engine runs all butterfly stages of an L-point sub-transform inside one
+// workgroup: each lane keeps P points in registers, runs radix-R butterflies
+// there, and stages exchange data through LDS (the "all the butterflies in
+// shared memory" idea of Sec. 2.3.2).  Stage twiddles W_{Ns*R}^{k*r} are read
+// from a per-(L, P) table built once per plan (the sin/cos look-up table of
+// Sec. 2.3.1); the reducibility of eq. 5 is what lets one table of an
+// L-point transform serve every radix inside it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace mfft {
+
+// ---------------------------------------------------------------------------
+// complex helpers (float2 = (re, im))
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// a * (-i)
+__device__ __forceinline__ float2 mul_negi(float2 a) { return make_float2(a.y, -a.x); }
+
+// x * W_64^e with W_64 = exp(-2*pi*i/64), e a compile-time constant after
+// unrolling (0 <= e < 64).  Exact forms for multiples of pi/4; otherwise the
+// cosine comes from a quarter-wave table of cos(2*pi*k/64), k = 0..16.
+__device__ __forceinline__ float2 mul_w64(float2 x, int e) {
+  constexpr float Q[17] = {
+      1.0f,                        0.995184726672196886244837f, 0.980785280403230449126182f,
+      0.956940335732208864935798f, 0.923879532511286756128183f, 0.881921264348355029712757f,
+      0.831469612302545237078788f, 0.773010453362736960810907f, 0.707106781186547524400844f,
+      0.634393284163645498215172f, 0.555570233019602224742831f, 0.471396736825997648556388f,
+      0.382683432365089771728460f, 0.290284677254462367636192f, 0.195090322016128267848285f,
+      0.098017140329560601994196f, 0.0f};
+  constexpr float R2 = 0.707106781186547524400844f;
+  e &= 63;
+  if (e == 0) return x;
+  if (e == 16) return make_float2(x.y, -x.x);
+  if (e == 32) return make_float2(-x.x, -x.y);
+  if (e == 48) return make_float2(-x.y, x.x);
+  if (e == 8) return make_float2((x.x + x.y) * R2, (x.y - x.x) * R2);
+  if (e == 24) return make_float2((x.y - x.x) * R2, -(x.x + x.y) * R2);
+  if (e == 40) return make_float2(-(x.x + x.y) * R2, (x.x - x.y) * R2);
+  if (e == 56) return make_float2((x.x - x.y) * R2, (x.x + x.y) * R2);
+  float c, s;  // W = (c, -s) with c = cos(2 pi e/64), s = sin(2 pi e/64)
+  if (e < 16) { c = Q[e]; s = Q[16 - e]; }
+  else if (e < 32) { c = -Q[32 - e]; s = Q[e - 16]; }
+  else if (e < 48) { c = -Q[e - 32]; s = -Q[48 - e]; }
+  else { c = Q[64 - e]; s = -Q[e - 48]; }
+  return make_float2(x.x * c + x.y * s, x.y * c - x.x * s);
+}
+
+// ---------------------------------------------------------------------------
+// forward DFT codelets in registers, natural order in and out:
+//   A[k] = sum_r a[r] W_R^{rk}
+// R = 2, 4 directly; larger R as an in-register four-step R = R1*R2 with
+// compile-time twiddles W_R^{n2*k1}.
+// ---------------------------------------------------------------------------
+template <int R> struct Dft;
+
+template <> struct Dft<1> {
+  __device__ __forceinline__ static void run(float2*) {}
+};
+template <> struct Dft<2> {
+  __device__ __forceinline__ static void run(float2* a) {
+    float2 t = csub(a[0], a[1]);
+    a[0] = cadd(a[0], a[1]);
+    a[1] = t;
+  }
+};
+template <> struct Dft<4> {
+  __device__ __forceinline__ static void run(float2* a) {
+    float2 t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+    float2 t2 = cadd(a[1], a[3]), t3 = mul_negi(csub(a[1], a[3]));
+    a[0] = cadd(t0, t2);
+    a[2] = csub(t0, t2);
+    a[1] = cadd(t1, t3);
+    a[3] = csub(t1, t3);
+  }
+};
+
+// R = R1 * R2: n = R2*n1 + n2, k = k1 + R1*k2.
+template <int R1, int R2> struct DftSplit {
+  static constexpr int R = R1 * R2;
+  __device__ __forceinline__ static void run(float2* a) {
+    float2 y[R];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+      float2 s[R1];
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) s[n1] = a[R2 * n1 + n2];
+      Dft<R1>::run(s);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) y[k1 * R2 + n2] = mul_w64(s[k1], (n2 * k1 * (64 / R)) & 63);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      Dft<R2>::run(&y[k1 * R2]);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) a[k1 + R1 * k2] = y[k1 * R2 + k2];
+    }
+  }
+};
+template <> struct Dft<8> {
+  __device__ __forceinline__ static void run(float2* a) { DftSplit<2, 4>::run(a); }
+};
+template <> struct Dft<16> {
+  __device__ __forceinline__ static void run(float2* a) { DftSplit<4, 4>::run(a); }
+};
+template <> struct Dft<32> {
+  __device__ __forceinline__ static void run(float2* a) { DftSplit<4, 8>::run(a); }
+};
+
+// ---------------------------------------------------------------------------
+// compile-time schedule of an L-point sub-transform with P points per lane
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
+
+template <int L, int P> struct Sched {
+  static_assert(L >= 2 && (L & (L - 1)) == 0, "L must be a power of two >= 2");
+  static constexpr int PP = P < L ? P : L;          // points per lane
+  static constexpr int T = L / PP;                  // lanes per line
+  static constexpr int LP = ilog2(PP);
+  static constexpr int S = (ilog2(L) + LP - 1) / LP;  // stages
+  static constexpr int FIRST = L >> ((S - 1) * LP);   // radix of stage 0
+  __host__ __device__ static constexpr int radix(int s) { return s == 0 ? FIRST : PP; }
+  __host__ __device__ static constexpr int ns(int s) { return s == 0 ? 1 : FIRST << ((s - 1) * LP); }
+  // stage s >= 1 reads W_{ns*R}^{k*r} at tw[off(s) + k*R + r]
+  __host__ __device__ static constexpr int off(int s) {
+    return s <= 1 ? 0 : off(s - 1) + ns(s - 1) * radix(s - 1);
+  }
+  static constexpr int TW = off(S);  // table entries
+};
+
+// LDS index of point e of line m; one pad slot per 16 points plus an odd
+// line stride keeps both lane patterns (stride across lines, stride 16
+// inside a line) spread over the banks.
+template <int L> struct LdsLayout {
+  static constexpr int LS = L + (L >> 4) + 1;
+  __device__ __forceinline__ static int idx(int m, int e) { return m * LS + e + (e >> 4); }
+};
+
+// ---------------------------------------------------------------------------
+// element storage types
+// ---------------------------------------------------------------------------
+struct c16bf { uint16_t x, y; };
+
+__device__ __forceinline__ float2 load_c(const float2* p) { return *p; }
+__device__ __forceinline__ float2 load_c(const __half2* p) { return __half22float2(*p); }
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+__device__ __forceinline__ float2 load_c(const c16bf* p) {
+  c16bf v = *p;
+  return make_float2(bf16_to_f32(v.x), bf16_to_f32(v.y));
+}
+__device__ __forceinline__ void store_c(float2* p, float2 v) { *p = v; }
+__device__ __forceinline__ void store_c(__half2* p, float2 v) {
+  *p = __halves2half2(__float2half_rn(v.x), __float2half_rn(v.y));
+}
+// float32 -> bfloat16, round to nearest, ties to even (NaN stays NaN).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ void store_c(c16bf* p, float2 v) {
+  c16bf o;
+  o.x = f32_to_bf16(v.x);
+  o.y = f32_to_bf16(v.y);
+  *p = o;
+}
+
+// ---------------------------------------------------------------------------
+// pass arguments (one kernel launch)
+// ---------------------------------------------------------------------------
+struct PassArgs {
+  const void* in;
+  void* out;
+  int64_t in_batch, out_batch;  // element stride between batches
+  int64_t in_line, out_line;    // element stride between adjacent lines
+  int64_t in_elem, out_elem;    // element stride between points of a line
+  int64_t total_tiles;          // tiles_per_batch * batch
+  int32_t tiles_per_batch;      // ceil(lines / W)
+  int32_t lines;                // lines per batch
+  const float2* tw;             // stage table of this (L, P)
+  const float2* tw_lo;          // inter-pass: W_N^{j & mask}
+  const float2* tw_hi;          // inter-pass: W_N^{(j >> shift) << shift}
+  int32_t tw_shift, tw_mask;
+  float scale;                  // applied to every output value
+  int32_t conj_in, conj_out;    // inverse direction: conj on first load / last store
+  int32_t xcd_remap;            // 1: consecutive tiles on one XCD
+};
+
+// Map a workgroup id to a tile so that tiles t, t+1, ... run on the same XCD
+// (workgroups are dealt round-robin to the 8 XCDs, each with its own L2).
+__device__ __forceinline__ int64_t tile_of(int64_t b, int64_t n, int remap) {
+  if (!remap || (n & 7)) return b;
+  return (b & 7) * (n >> 3) + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// The engine: all stages of W independent L-point transforms held by one
+// workgroup, P points per lane.  On entry lane (m, t) holds points t + q*T of
+// line m in v[q]; on exit lane (m_st, t_st) holds outputs t_st + q*T of line
+// m_st (natural order).  Stage s (radix R, span NS) is a Stockham
+// (self-sorting) decimation-in-time step: butterfly j takes points
+// j + r*L/R, multiplies them by W_{NS*R}^{(j mod NS)*r}, runs an R-point DFT
+// and writes output r to (j div NS)*NS*R + (j mod NS) + r*NS.  The lane
+// mapping switches from (m, t) to (m_st, t_st) at the first LDS exchange.
+// ---------------------------------------------------------------------------
+template <int L, int P, int W>
+__device__ __forceinline__ void run_stages(float2* v, float2* lds, int& m, int& t,
+                                           int m_st, int t_st, bool remap,
+                                           const float2* __restrict__ twt) {
+  using S = Sched<L, P>;
+  using LY = LdsLayout<L>;
+  constexpr int T = S::T;
+  constexpr int PP = S::PP;
+#pragma unroll
+  for (int s = 0; s < S::S; ++s) {
+    const int R = S::radix(s);
+    const int NS = S::ns(s);
+    const int NB = PP / R;
+    const bool last = (s == S::S - 1);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = t + b * T;
+      const int k = j & (NS - 1);
+      float2 x[PP];
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = v[b + r * NB];
+      if (s > 0) {
+        const float2* tw = twt + S::off(s) + k * R;
+#pragma unroll
+        for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[r]);
+      }
+      switch (R) {
+        case 2: Dft<2>::run(x); break;
+        case 4: Dft<4>::run(x); break;
+        case 8: Dft<8>::run(x); break;
+        case 16: Dft<16>::run(x); break;
+        case 32: Dft<32>::run(x); break;
+        default: break;
+      }
+      if (last) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b + r * NB] = x[r];
+      } else {
+        const int o0 = (j / NS) * NS * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[LY::idx(m, o0 + r * NS)] = x[r];
+      }
+    }
+    if (!last) {
+      __syncthreads();
+      m = m_st;
+      t = t_st;
+#pragma unroll
+      for (int q = 0; q < PP; ++q) v[q] = lds[LY::idx(m, t + q * T)];
+      __syncthreads();
+    }
+  }
+  if (S::S == 1 && remap) {
+    // one-stage transform whose load and store mappings differ: transpose
+    // through LDS (`remap` is uniform across the workgroup)
+#pragma unroll
+    for (int q = 0; q < PP; ++q) lds[LY::idx(m, t + q * T)] = v[q];
+    __syncthreads();
+    m = m_st;
+    t = t_st;
+#pragma unroll
+    for (int q = 0; q < PP; ++q) v[q] = lds[LY::idx(m, t + q * T)];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The strip pass.  A workgroup transforms W lines ("a strip") of L points.
+// Lane mapping: LOADM/STOREM = 1 puts the line index m fastest across lanes
+// (W adjacent lines of a strided view -> W-wide contiguous segments), 0 puts
+// the point index fastest (contiguous lines).  With TWID the outputs are
+// multiplied by W_N^{line*k} (the inter-pass twiddle of the N1 x N2 split).
+// ---------------------------------------------------------------------------
+template <int L, int P, int W, int LOADM, int STOREM, bool TWID, typename TS>
+__global__ void __launch_bounds__((W * Sched<L, P>::T))
+k_strip(PassArgs a) {
+  using S = Sched<L, P>;
+  using LY = LdsLayout<L>;
+  constexpr int T = S::T;
+  constexpr int PP = S::PP;
+  __shared__ float2 lds[W * LY::LS];
+
+  const int tid = threadIdx.x;
+  const int64_t tile = tile_of(blockIdx.x, a.total_tiles, a.xcd_remap);
+  const int64_t bat = tile / a.tiles_per_batch;
+  const int line0 = (int)(tile - bat * a.tiles_per_batch) * W;
+
+  int m = LOADM ? tid % W : tid / T;
+  int t = LOADM ? tid / W : tid % T;
+  const int m_st = STOREM ? tid % W : tid / T;
+  const int t_st = STOREM ? tid / W : tid % T;
+
+  float2 v[PP];
+  {
+    const TS* src = reinterpret_cast<const TS*>(a.in) + bat * a.in_batch;
+    const bool ok = line0 + m < a.lines;
+    const int64_t base = (int64_t)(line0 + m) * a.in_line;
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+      v[q] = ok ? load_c(src + base + (int64_t)(t + q * T) * a.in_elem) : make_float2(0.f, 0.f);
+      if (a.conj_in) v[q].y = -v[q].y;
+    }
+  }
+
+  run_stages<L, P, W>(v, lds, m, t, m_st, t_st, LOADM != STOREM, a.tw);
+
+  // epilogue: inter-pass twiddle, scale, conjugate, store
+  {
+    TS* dst = reinterpret_cast<TS*>(a.out) + bat * a.out_batch;
+    const int line = line0 + m;
+    const bool ok = line < a.lines;
+    const int64_t base = (int64_t)line * a.out_line;
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+      const int e = t + q * T;
+      float2 y = v[q];
+      if (TWID) {
+        const uint32_t jj = (uint32_t)line * (uint32_t)e;
+        const float2 w = cmul(a.tw_hi[jj >> a.tw_shift], a.tw_lo[jj & (uint32_t)a.tw_mask]);
+        y = cmul(y, w);
+      }
+      y = cscale(y, a.scale);
+      if (a.conj_out) y.y = -y.y;
+      if (ok) store_c(dst + base + (int64_t)e * a.out_elem, y);
+    }
+  }
+}
+
+// Length-1 transforms and other trivial cases: out = scale * in (conj is a
+// no-op pair for length 1).
+template <typename TS>
+__global__ void __launch_bounds__(256) k_scale_copy(const TS* in, TS* out, int64_t n, float scale) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) store_c(out + i, cscale(load_c(in + i), scale));
+}
+
+}  // namespace mfft

@@ -1,0 +1,1036 @@
+// Host runtime of the MI355X FFT: variant registry, planning (pass count,
+// N1 x N2 split, variant choice), twiddle tables, and the C ABI of mi355fft.h.
+//
+// Planning follows Sec. 2.3.2: a transform whose length fits one workgroup's
+// LDS is done in one kernel; a longer 1-D transform is split in global memory
+// as N = N1*N2 into two kernels (N1-point column transforms with the twiddle
+// W_N^{n2*k1} fused into their store, then N2-point column transforms), the
+// kernel boundary being the only global synchronisation; a 2-D transform is a
+// row kernel followed by a column kernel (rows first, then columns).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mi355fft.h"
+#include "many.hpp"
+#include "twiddle.hpp"
+#include "variants.hpp"
+
+using namespace mfft;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return FFT_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// variant registry
+// ---------------------------------------------------------------------------
+std::vector<Variant>* g_variants = nullptr;
+std::once_flag g_variants_once;
+
+void add_one(const Variant& v) { g_variants->push_back(v); }
+
+const std::vector<Variant>& variants() {
+  std::call_once(g_variants_once, [] {
+    g_variants = new std::vector<Variant>();
+    add_variants_c64_row(add_one);
+    add_variants_c64_a(add_one);
+    add_variants_c64_col(add_one);
+    add_variants_c16(add_one);
+  });
+  return *g_variants;
+}
+
+const Variant* find_by_name(const std::string& name) {
+  for (const Variant& v : variants())
+    if (name == v.name) return &v;
+  return nullptr;
+}
+
+// Best variant of a role/length/dtype: prefer P = 16, then the W closest to
+// `want_w` from below (never more lines than there are to transform, when
+// some variant allows that), then the thread count closest to 256.
+const Variant* pick(int role, int L, int dtype, int want_w, int64_t lines) {
+  const Variant* best = nullptr;
+  double best_score = 1e300;
+  for (const Variant& v : variants()) {
+    if (v.role != role || v.L != L || v.dtype != dtype) continue;
+    double score = 0;
+    score += (v.P == 16 || v.P == v.L) ? 0 : 1000;
+    const int w_cap = (int)std::max<int64_t>(1, std::min<int64_t>(want_w, lines));
+    score += v.W > w_cap ? 100.0 * v.W / w_cap : 10.0 * std::fabs(std::log2((double)w_cap / v.W));
+    score += std::fabs(std::log2(v.threads / 256.0));
+    if (score < best_score) {
+      best_score = score;
+      best = &v;
+    }
+  }
+  return best;
+}
+
+int ilog2_64(int64_t v) {
+  int r = 0;
+  while (((int64_t)1 << r) < v) ++r;
+  return r;
+}
+bool pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
+size_t esize(int dtype) { return dtype == FFT_C64 ? 8 : 4; }
+
+// ---------------------------------------------------------------------------
+// schedule (host-only description of the launches)
+// ---------------------------------------------------------------------------
+enum Sel { SEL_IN = 0, SEL_OUT = 1, SEL_WS = 2 };
+
+struct PassSpec {
+  const Variant* v = nullptr;  // nullptr: copy-scale
+  PassArgs args{};
+  int src = SEL_IN, dst = SEL_OUT;
+  int64_t copy_n = 0;          // copy-scale: points
+  bool first = false, last = false;
+};
+
+struct Schedule {
+  std::vector<PassSpec> passes;
+  int64_t split[2] = {0, 0};
+  int64_t points = 0;
+  bool inplace_needs_ws = false;
+};
+
+struct Overrides {
+  int64_t split = 0;
+  std::string a, b, row, col, single;
+};
+
+int parse_schedule(const char* s, Overrides* o) {
+  if (!s) return FFT_OK;
+  std::string str(s);
+  size_t pos = 0;
+  while (pos < str.size()) {
+    size_t end = str.find(';', pos);
+    if (end == std::string::npos) end = str.size();
+    std::string item = str.substr(pos, end - pos);
+    pos = end + 1;
+    if (item.empty()) continue;
+    size_t eq = item.find('=');
+    if (eq == std::string::npos) return FFT_ERR_INVALID_ARGUMENT;
+    std::string key = item.substr(0, eq), val = item.substr(eq + 1);
+    if (key == "split") {
+      char* e = nullptr;
+      long long v = strtoll(val.c_str(), &e, 10);
+      if (!e || *e || v < 1) return FFT_ERR_INVALID_ARGUMENT;
+      o->split = v;
+    } else if (key == "a") o->a = val;
+    else if (key == "b") o->b = val;
+    else if (key == "row") o->row = val;
+    else if (key == "col") o->col = val;
+    else if (key == "single") o->single = val;
+    else return FFT_ERR_INVALID_ARGUMENT;
+  }
+  return FFT_OK;
+}
+
+// Resolve an override name (must match role, L and dtype) or pick a default.
+int choose(const std::string& name, int role, int L, int dtype, int want_w, int64_t lines,
+           const Variant** out) {
+  if (!name.empty()) {
+    const Variant* v = find_by_name(name);
+    if (!v || v->role != role || v->L != L || v->dtype != dtype) return FFT_ERR_INVALID_ARGUMENT;
+    *out = v;
+    return FFT_OK;
+  }
+  *out = pick(role, L, dtype, want_w, lines);
+  return *out ? FFT_OK : FFT_ERR_UNSUPPORTED_SIZE;
+}
+
+constexpr int kSingleMaxLog2 = 14;  // one-kernel transforms up to 2^14 points
+constexpr int kSplitMinLog2 = 6, kSplitMaxLog2 = 12;
+
+int build_schedule(const int64_t* n, int64_t batch, int dims, int dtype, const char* sched,
+                   Schedule* out) {
+  if (!n || batch < 1 || (dims != 1 && dims != 2)) return FFT_ERR_INVALID_ARGUMENT;
+  if (dtype != FFT_C64 && dtype != FFT_C16F && dtype != FFT_C16BF) return FFT_ERR_INVALID_ARGUMENT;
+  Overrides ov;
+  if (parse_schedule(sched, &ov) != FFT_OK) return FFT_ERR_INVALID_ARGUMENT;
+  Schedule S;
+  if (dims == 1) {
+    const int64_t N = n[0];
+    if (!pow2(N) || ilog2_64(N) > FFT_MAX_LOG2_1D) return FFT_ERR_UNSUPPORTED_SIZE;
+    if (batch > ((int64_t)1 << 40) / N) return FFT_ERR_UNSUPPORTED_SIZE;
+    S.points = N * batch;
+    const int l = ilog2_64(N);
+    if (N == 1) {
+      PassSpec p;
+      p.copy_n = batch;
+      p.first = p.last = true;
+      S.passes.push_back(p);
+    } else if (l <= kSingleMaxLog2 && ov.split == 0) {
+      PassSpec p;
+      int rc = choose(ov.single.empty() ? ov.row : ov.single, ROLE_ROW, (int)N, dtype, 64, batch, &p.v);
+      if (rc) return rc;
+      PassArgs& a = p.args;
+      a.in_batch = a.out_batch = 0;
+      a.in_line = a.out_line = N;
+      a.in_elem = a.out_elem = 1;
+      a.lines = (int32_t)std::min<int64_t>(batch, INT32_MAX);
+      if (batch > INT32_MAX) return FFT_ERR_UNSUPPORTED_SIZE;
+      a.tiles_per_batch = (int32_t)((batch + p.v->W - 1) / p.v->W);
+      a.total_tiles = a.tiles_per_batch;
+      p.first = p.last = true;
+      S.passes.push_back(p);
+    } else {
+      int64_t N1 = ov.split ? ov.split : ((int64_t)1 << ((l + 1) / 2));
+      if (!pow2(N1) || N1 < 2 || N1 >= N) return FFT_ERR_INVALID_ARGUMENT;
+      int64_t N2 = N / N1;
+      if (ilog2_64(N1) > kSingleMaxLog2 || ilog2_64(N2) > kSingleMaxLog2) return FFT_ERR_UNSUPPORTED_SIZE;
+      S.split[0] = N1;
+      S.split[1] = N2;
+      PassSpec A, B;
+      int rc = choose(ov.a, ROLE_SPLIT_A, (int)N1, dtype, 16, N2, &A.v);
+      if (rc) return rc;
+      rc = choose(ov.b.empty() ? ov.col : ov.b, ROLE_COL, (int)N2, dtype, 16, N1, &B.v);
+      if (rc) return rc;
+      // pass A: x viewed as [N1][N2]; line n2 (column), point n1; writes
+      // T[n2*N1 + k1] times W_N^{n2*k1}.
+      PassArgs& a = A.args;
+      a.in_batch = a.out_batch = N;
+      a.in_line = 1;
+      a.in_elem = N2;
+      a.out_line = N1;
+      a.out_elem = 1;
+      a.lines = (int32_t)N2;
+      a.tiles_per_batch = (int32_t)((N2 + A.v->W - 1) / A.v->W);
+      a.total_tiles = (int64_t)a.tiles_per_batch * batch;
+      a.tw_shift = (l + 1) / 2;
+      a.tw_mask = (1 << a.tw_shift) - 1;
+      A.first = true;
+      // pass B: T viewed as [N2][N1]; line k1 (column), point n2; writes
+      // X[k1 + N1*k2] in place of its own columns.
+      PassArgs& b = B.args;
+      b.in_batch = b.out_batch = N;
+      b.in_line = b.out_line = 1;
+      b.in_elem = b.out_elem = N1;
+      b.lines = (int32_t)N1;
+      b.tiles_per_batch = (int32_t)((N1 + B.v->W - 1) / B.v->W);
+      b.total_tiles = (int64_t)b.tiles_per_batch * batch;
+      B.last = true;
+      A.src = SEL_IN;
+      A.dst = SEL_OUT;
+      B.src = SEL_OUT;
+      B.dst = SEL_OUT;
+      S.inplace_needs_ws = true;
+      S.passes.push_back(A);
+      S.passes.push_back(B);
+      if (a.total_tiles > INT32_MAX || b.total_tiles > INT32_MAX) return FFT_ERR_UNSUPPORTED_SIZE;
+    }
+  } else {
+    const int64_t R = n[0], C = n[1];
+    if (!pow2(R) || !pow2(C) || ilog2_64(R) > FFT_MAX_LOG2_2D || ilog2_64(C) > FFT_MAX_LOG2_2D)
+      return FFT_ERR_UNSUPPORTED_SIZE;
+    if (batch > ((int64_t)1 << 40) / (R * C)) return FFT_ERR_UNSUPPORTED_SIZE;
+    S.points = R * C * batch;
+    if (C > 1) {
+      PassSpec p;
+      int rc = choose(ov.row, ROLE_ROW, (int)C, dtype, 64, R * batch, &p.v);
+      if (rc) return rc;
+      PassArgs& a = p.args;
+      a.in_batch = a.out_batch = 0;
+      a.in_line = a.out_line = C;
+      a.in_elem = a.out_elem = 1;
+      if (R * batch > INT32_MAX) return FFT_ERR_UNSUPPORTED_SIZE;
+      a.lines = (int32_t)(R * batch);
+      a.tiles_per_batch = (int32_t)((R * batch + p.v->W - 1) / p.v->W);
+      a.total_tiles = a.tiles_per_batch;
+      p.src = SEL_IN;
+      p.dst = SEL_OUT;
+      S.passes.push_back(p);
+    }
+    if (R > 1) {
+      PassSpec p;
+      int rc = choose(ov.col, ROLE_COL, (int)R, dtype, 16, C, &p.v);
+      if (rc) return rc;
+      PassArgs& a = p.args;
+      a.in_batch = a.out_batch = R * C;
+      a.in_line = a.out_line = 1;
+      a.in_elem = a.out_elem = C;
+      a.lines = (int32_t)C;
+      a.tiles_per_batch = (int32_t)((C + p.v->W - 1) / p.v->W);
+      a.total_tiles = (int64_t)a.tiles_per_batch * batch;
+      if (a.total_tiles > INT32_MAX) return FFT_ERR_UNSUPPORTED_SIZE;
+      p.src = S.passes.empty() ? SEL_IN : SEL_OUT;
+      p.dst = SEL_OUT;
+      S.passes.push_back(p);
+    }
+    if (S.passes.empty()) {
+      PassSpec p;
+      p.copy_n = batch;
+      S.passes.push_back(p);
+    }
+    S.passes.front().first = true;
+    S.passes.back().last = true;
+  }
+  *out = S;
+  return FFT_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan object
+// ---------------------------------------------------------------------------
+struct fft_plan_s {
+  int kind = 0;  // 0 = strided passes, 1 = batched uneven (many)
+  int64_t n[2] = {1, 1};
+  int dims = 1, dtype = 0, direction = -1;
+  int64_t batch = 1;
+  double scale = 1.0;
+  bool scale_user = false;
+  Schedule sched;
+  float2* d_tables = nullptr;
+  size_t table_bytes = 0;
+  bool gpu_twiddles = false;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  int device = 0;
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<double> prof_ms;
+  std::vector<int64_t> prof_n;
+  bool prof_pending = false;
+  // batched uneven sizes
+  ManyPlan many;
+};
+
+namespace {
+
+// Append (L, P) stage tables and the split's inter-pass tables to `segs`,
+// recording offsets in the pass arguments (resolved to pointers later).
+struct TableBuild {
+  std::vector<TwSeg> segs;
+  int64_t total = 0;
+  std::map<std::pair<int, int>, int64_t> stage_off;
+  int64_t add(int64_t count, int64_t R, int64_t M, int64_t mul) {
+    TwSeg s{total, count, R, M, mul};
+    segs.push_back(s);
+    total += count;
+    return s.off;
+  }
+  // one segment per stage s >= 1 of the (L, P) schedule
+  int64_t add_stage_table(int L, int P) {
+    auto key = std::make_pair(L, P);
+    auto it = stage_off.find(key);
+    if (it != stage_off.end()) return it->second;
+    const int lp = ilog2(P < L ? P : L);
+    const int PP = 1 << lp;
+    const int S = (ilog2(L) + lp - 1) / lp;
+    const int FIRST = L >> ((S - 1) * lp);
+    const int64_t start = total;
+    int ns = FIRST;
+    for (int s = 1; s < S; ++s) {
+      add((int64_t)ns * PP, PP, (int64_t)ns * PP, 0);
+      ns *= PP;
+    }
+    if (total == start) add(1, 0, 1, 0);  // one-stage transform: placeholder entry
+    stage_off[key] = start;
+    return start;
+  }
+};
+
+void host_fill(const std::vector<TwSeg>& segs, std::vector<float2>& tab) {
+  for (const TwSeg& s : segs)
+    for (int64_t i = 0; i < s.count; ++i) {
+      double c, sn;
+      twiddle_fp64(seg_exponent(s, i), s.M, &c, &sn);
+      tab[s.off + i] = make_float2((float)c, (float)-sn);
+    }
+}
+
+int upload_tables(fft_plan_s* p, TableBuild& tb, bool on_gpu) {
+  const size_t bytes = (size_t)std::max<int64_t>(tb.total, 1) * sizeof(float2);
+  hipError_t e = hipMalloc((void**)&p->d_tables, bytes);
+  if (e != hipSuccess) {
+    p->d_tables = nullptr;
+    return e == hipErrorOutOfMemory ? FFT_ERR_NO_MEMORY : hip_fail(e);
+  }
+  p->table_bytes = bytes;
+  if (!on_gpu) {
+    std::vector<float2> tab((size_t)std::max<int64_t>(tb.total, 1));
+    host_fill(tb.segs, tab);
+    e = hipMemcpy(p->d_tables, tab.data(), (size_t)tb.total * sizeof(float2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e);
+    return FFT_OK;
+  }
+  // float64 generation on the GPU: upload the segment list, run the kernel
+  TwSeg* d_segs = nullptr;
+  e = hipMalloc((void**)&d_segs, tb.segs.size() * sizeof(TwSeg));
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? FFT_ERR_NO_MEMORY : hip_fail(e);
+  e = hipMemcpy(d_segs, tb.segs.data(), tb.segs.size() * sizeof(TwSeg), hipMemcpyHostToDevice);
+  int64_t maxc = 1;
+  for (const TwSeg& s : tb.segs) maxc = std::max(maxc, s.count);
+  if (e == hipSuccess) e = launch_twiddle_fp64(p->d_tables, d_segs, (int)tb.segs.size(), maxc, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  hipFree(d_segs);
+  if (e != hipSuccess) return hip_fail(e);
+  p->gpu_twiddles = true;
+  return FFT_OK;
+}
+
+void set_default_scale(fft_plan_s* p) {
+  double total = 1;
+  if (p->kind == 0) total = (double)p->n[0] * (double)(p->dims == 2 ? p->n[1] : 1);
+  p->scale = p->direction > 0 ? 1.0 / total : 1.0;
+}
+
+int check_ptr(const void* ptr, int dtype) {
+  return ((uintptr_t)ptr % esize(dtype)) ? FFT_ERR_ALIGNMENT : FFT_OK;
+}
+
+constexpr int kGpuTwiddleMinLog2 = 22;
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// batched uneven sizes: host side of the persistent launch
+// ---------------------------------------------------------------------------
+namespace mfft {
+
+size_t many_workspace_bytes(const ManyPlan& mp) {
+  return (size_t)(kManyWsHeader + mp.count) * sizeof(int32_t);
+}
+
+hipError_t many_reset_workspace(const ManyPlan& mp, void* ws) {
+  return hipMemset(ws, 0, many_workspace_bytes(mp));
+}
+
+int many_alloc_workspace(const ManyPlan& mp, void** ws, size_t* bytes) {
+  const size_t b = many_workspace_bytes(mp);
+  hipError_t e = hipMalloc(ws, b);
+  if (e != hipSuccess) {
+    *ws = nullptr;
+    if (e == hipErrorOutOfMemory) return FFT_ERR_NO_MEMORY;
+    g_last_hip = (int)e;
+    return FFT_ERR_HIP;
+  }
+  e = hipMemset(*ws, 0, b);
+  if (e != hipSuccess) {
+    hipFree(*ws);
+    *ws = nullptr;
+    g_last_hip = (int)e;
+    return FFT_ERR_HIP;
+  }
+  *bytes = b;
+  return FFT_OK;
+}
+
+hipError_t many_launch(const ManyPlan& mp, const void* in, void* out, void* ws, float scale,
+                       bool use_scale, bool inverse, hipStream_t s) {
+  if (!ws) return hipErrorInvalidValue;
+  ManyArgs a = mp.args;
+  a.in = in;
+  a.out = out;
+  a.ws = (int32_t*)ws;
+  a.scale = scale;
+  a.use_scale = use_scale ? 1 : 0;
+  a.inverse = inverse ? 1 : 0;
+  return mp.var->launch(a, mp.grid, s);
+}
+
+void many_free(ManyPlan& mp) {
+  if (mp.d_items) hipFree(mp.d_items);
+  if (mp.d_xf) hipFree(mp.d_xf);
+  if (mp.d_order) hipFree(mp.d_order);
+  mp.d_items = nullptr;
+  mp.d_xf = nullptr;
+  mp.d_order = nullptr;
+  mp.active = false;
+}
+
+}  // namespace mfft
+
+namespace {
+
+struct ManyOptions {
+  int P = 16, threads = 256, pass2 = 13;
+  bool given_order = false;
+};
+
+int parse_many_schedule(const char* s, ManyOptions* o) {
+  if (!s) return FFT_OK;
+  std::string str(s);
+  size_t pos = 0;
+  while (pos < str.size()) {
+    size_t end = str.find(';', pos);
+    if (end == std::string::npos) end = str.size();
+    std::string item = str.substr(pos, end - pos);
+    pos = end + 1;
+    if (item.empty()) continue;
+    size_t eq = item.find('=');
+    if (eq == std::string::npos) return FFT_ERR_INVALID_ARGUMENT;
+    std::string key = item.substr(0, eq), val = item.substr(eq + 1);
+    if (key == "order") {
+      if (val == "given") o->given_order = true;
+      else if (val == "bigfirst") o->given_order = false;
+      else return FFT_ERR_INVALID_ARGUMENT;
+      continue;
+    }
+    char* e = nullptr;
+    long v = strtol(val.c_str(), &e, 10);
+    if (!e || *e) return FFT_ERR_INVALID_ARGUMENT;
+    if (key == "p") o->P = (int)v;
+    else if (key == "threads") o->threads = (int)v;
+    else if (key == "pass2") o->pass2 = (int)v;
+    else return FFT_ERR_INVALID_ARGUMENT;
+  }
+  return FFT_OK;
+}
+
+// lines of a 2^lg tile in a workgroup of `threads` lanes, P points per lane
+int tile_lines(int lg, int P, int threads) {
+  if (lg == 0) return threads;
+  const int L = 1 << lg;
+  const int T = L / std::min(P, L);
+  return threads / T;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direction,
+                const char* schedule, fft_plan_t* out) {
+  if (!out) return FFT_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  if (direction != FFT_FORWARD && direction != FFT_INVERSE) return FFT_ERR_INVALID_ARGUMENT;
+  Schedule S;
+  int rc = build_schedule(n, batch, dims, dtype, schedule, &S);
+  if (rc) return rc;
+  fft_plan_s* p = new (std::nothrow) fft_plan_s();
+  if (!p) return FFT_ERR_NO_MEMORY;
+  p->kind = 0;
+  p->dims = dims;
+  p->n[0] = n[0];
+  p->n[1] = dims == 2 ? n[1] : 1;
+  p->batch = batch;
+  p->dtype = dtype;
+  p->direction = direction;
+  p->sched = S;
+  set_default_scale(p);
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e);
+  }
+  // twiddle tables
+  TableBuild tb;
+  std::vector<int64_t> stage_off(S.passes.size(), 0);
+  int64_t lo_off = -1, hi_off = -1;
+  for (size_t i = 0; i < S.passes.size(); ++i) {
+    const PassSpec& ps = S.passes[i];
+    if (!ps.v) continue;
+    stage_off[i] = tb.add_stage_table(ps.v->L, ps.v->P);
+    if (ps.v->role == ROLE_SPLIT_A) {
+      const int64_t N = n[0];
+      const int sh = ps.args.tw_shift;
+      lo_off = tb.add((int64_t)1 << sh, 0, N, 1);
+      hi_off = tb.add(N >> sh, 0, N, (int64_t)1 << sh);
+    }
+  }
+  const bool on_gpu = dims == 1 && ilog2_64(n[0]) >= kGpuTwiddleMinLog2;
+  rc = upload_tables(p, tb, on_gpu);
+  if (rc) {
+    fft_destroy(p);
+    return rc;
+  }
+  for (size_t i = 0; i < p->sched.passes.size(); ++i) {
+    PassSpec& ps = p->sched.passes[i];
+    if (!ps.v) continue;
+    ps.args.tw = p->d_tables + stage_off[i];
+    if (ps.v->role == ROLE_SPLIT_A) {
+      ps.args.tw_lo = p->d_tables + lo_off;
+      ps.args.tw_hi = p->d_tables + hi_off;
+    }
+  }
+  *out = p;
+  return FFT_OK;
+}
+
+int fft_plan(const int64_t* n, int64_t batch, int dims, int dtype, int direction, fft_plan_t* out) {
+  return fft_plan_ex(n, batch, dims, dtype, direction, nullptr, out);
+}
+
+int fft_set_scale(fft_plan_t p, double scale) {
+  if (!p || !std::isfinite(scale)) return FFT_ERR_INVALID_ARGUMENT;
+  p->scale = scale;
+  p->scale_user = true;
+  return FFT_OK;
+}
+
+int fft_workspace_size(fft_plan_t p, size_t* bytes) {
+  if (!p || !bytes) return FFT_ERR_INVALID_ARGUMENT;
+  if (p->kind == 1) *bytes = many_workspace_bytes(p->many);
+  else *bytes = p->sched.inplace_needs_ws ? (size_t)p->sched.points * esize(p->dtype) : 0;
+  return FFT_OK;
+}
+
+int fft_set_workspace(fft_plan_t p, void* ptr, size_t bytes) {
+  if (!p) return FFT_ERR_INVALID_ARGUMENT;
+  size_t need = 0;
+  fft_workspace_size(p, &need);
+  if (ptr && bytes < need) return FFT_ERR_INVALID_ARGUMENT;
+  if (ptr && ((uintptr_t)ptr % 16)) return FFT_ERR_ALIGNMENT;
+  if (p->ws_owned && p->ws) {
+    hipFree(p->ws);
+  }
+  p->ws_owned = false;
+  p->ws = ptr;
+  p->ws_bytes = ptr ? bytes : 0;
+  if (!ptr && p->kind == 1) {
+    // back to a plan-owned queue workspace
+    int rc = many_alloc_workspace(p->many, &p->ws, &p->ws_bytes);
+    if (rc) return rc == FFT_ERR_HIP ? hip_fail((hipError_t)g_last_hip) : rc;
+    p->ws_owned = true;
+  } else if (ptr && p->kind == 1) {
+    hipError_t e = many_reset_workspace(p->many, ptr);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return FFT_OK;
+}
+
+int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
+  if (!p || !in || !out) return FFT_ERR_INVALID_ARGUMENT;
+  if (check_ptr(in, p->dtype) || check_ptr(out, p->dtype)) return FFT_ERR_ALIGNMENT;
+  hipStream_t s = (hipStream_t)stream;
+  if (p->kind == 1) {
+    int prof = p->prof && !p->ev.empty();
+    if (prof) hipEventRecord(p->ev[0], s);
+    if (p->many.has_split && in == out) return FFT_ERR_INPLACE;
+    hipError_t e = many_launch(p->many, in, out, p->ws, (float)p->scale, p->scale_user, p->direction > 0, s);
+    if (prof) hipEventRecord(p->ev[1], s);
+    if (e != hipSuccess) return hip_fail(e);
+    p->prof_pending = prof;
+    return FFT_OK;
+  }
+  const Schedule& S = p->sched;
+  const size_t bytes = (size_t)S.points * esize(p->dtype);
+  const char* ib = (const char*)in;
+  const char* ob = (const char*)out;
+  const bool overlap = ib < ob + bytes && ob < ib + bytes;
+  const bool same = in == out;
+  if (overlap && !same) return FFT_ERR_INPLACE;
+  void* ws = nullptr;
+  if (same && S.passes.size() > 1 && S.inplace_needs_ws) {
+    if (!p->ws) return FFT_ERR_INPLACE;
+    ws = p->ws;
+  }
+  const bool inv = p->direction > 0;
+  for (size_t i = 0; i < S.passes.size(); ++i) {
+    const PassSpec& ps = S.passes[i];
+    // out of place: each pass reads `in` (first) or `out` and writes `out`;
+    // in place with a workspace: A reads in and writes ws, B reads ws, writes out
+    void* src = ws ? (i == 0 ? (void*)in : ws) : (ps.src == SEL_IN ? (void*)in : out);
+    void* dst = ws ? (i == 0 ? ws : out) : out;
+    if (p->prof && 2 * i + 1 < p->ev.size()) hipEventRecord(p->ev[2 * i], s);
+    hipError_t e;
+    if (!ps.v) {
+      e = launch_scale_copy(p->dtype, src, dst, ps.copy_n, (float)p->scale, s);
+    } else {
+      PassArgs a = ps.args;
+      a.in = src;
+      a.out = dst;
+      a.scale = ps.last ? (float)p->scale : 1.0f;
+      a.conj_in = (inv && ps.first) ? 1 : 0;
+      a.conj_out = (inv && ps.last) ? 1 : 0;
+      e = ps.v->launch(a, s);
+    }
+    if (p->prof && 2 * i + 1 < p->ev.size()) hipEventRecord(p->ev[2 * i + 1], s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  p->prof_pending = p->prof;
+  return FFT_OK;
+}
+
+int fft_plan_info(fft_plan_t p, fft_plan_info_t* info) {
+  if (!p || !info) return FFT_ERR_INVALID_ARGUMENT;
+  memset(info, 0, sizeof(*info));
+  info->n[0] = p->n[0];
+  info->n[1] = p->n[1];
+  info->batch = p->batch;
+  info->dims = p->dims;
+  info->dtype = p->dtype;
+  info->direction = p->direction;
+  info->gpu_twiddles = p->gpu_twiddles ? 1 : 0;
+  const double es = (double)esize(p->dtype);
+  if (p->kind == 1) {
+    info->passes = 1;
+    snprintf(info->pass_variant[0], 32, "%s", "persistent_many");
+    info->points = p->many.points;
+    info->flops = p->many.flops;
+    info->bytes_min = 2.0 * es * (double)p->many.points;
+    info->bytes_pass[0] = 2.0 * es * (double)p->many.pass_points;
+    return FFT_OK;
+  }
+  const Schedule& S = p->sched;
+  info->passes = (int)S.passes.size();
+  info->split[0] = S.split[0];
+  info->split[1] = S.split[1];
+  info->points = S.points;
+  const double N = (double)p->n[0] * (double)p->n[1];
+  info->flops = 5.0 * N * std::log2(std::max(N, 1.0)) * (double)p->batch;
+  info->bytes_min = 2.0 * es * (double)S.points;
+  for (size_t i = 0; i < S.passes.size() && i < 4; ++i) {
+    snprintf(info->pass_variant[i], 32, "%s", S.passes[i].v ? S.passes[i].v->name : "copy_scale");
+    info->bytes_pass[i] = 2.0 * es * (double)S.points;
+  }
+  return FFT_OK;
+}
+
+int fft_destroy(fft_plan_t p) {
+  if (!p) return FFT_OK;
+  for (hipEvent_t e : p->ev) hipEventDestroy(e);
+  if (p->d_tables) hipFree(p->d_tables);
+  if (p->ws_owned && p->ws) hipFree(p->ws);
+  many_free(p->many);
+  delete p;
+  return FFT_OK;
+}
+
+const char* fft_error_string(int status) {
+  switch (status) {
+    case FFT_OK: return "ok";
+    case FFT_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case FFT_ERR_UNSUPPORTED_SIZE: return "unsupported size (not a power of two, or out of range)";
+    case FFT_ERR_ALIGNMENT: return "pointer not aligned to the element size";
+    case FFT_ERR_INPLACE: return "in-place or overlapping multi-pass exec needs a workspace";
+    case FFT_ERR_HIP: return "HIP runtime error (see fft_last_hip_error)";
+    case FFT_ERR_NO_MEMORY: return "out of memory";
+    case FFT_ERR_WATCHDOG: return "batched kernel wait limit expired";
+    default: return "unknown status";
+  }
+}
+
+int fft_last_hip_error(void) { return g_last_hip; }
+
+int fft_variant_count(void) { return (int)variants().size(); }
+
+const char* fft_variant_name(int i) {
+  if (i < 0 || i >= (int)variants().size()) return nullptr;
+  return variants()[i].name;
+}
+
+int fft_variant_describe(int i, int* L, int* P, int* W, int* threads, int* role, int* dtype) {
+  if (i < 0 || i >= (int)variants().size()) return FFT_ERR_INVALID_ARGUMENT;
+  const Variant& v = variants()[i];
+  if (L) *L = v.L;
+  if (P) *P = v.P;
+  if (W) *W = v.W;
+  if (threads) *threads = v.threads;
+  if (role) *role = v.role;
+  if (dtype) *dtype = v.dtype;
+  return FFT_OK;
+}
+
+int fft_describe(const int64_t* n, int64_t batch, int dims, int dtype, const char* schedule,
+                 int* passes, char names[4][32], int64_t split[2]) {
+  Schedule S;
+  int rc = build_schedule(n, batch, dims, dtype, schedule, &S);
+  if (rc) return rc;
+  if (passes) *passes = (int)S.passes.size();
+  if (names)
+    for (size_t i = 0; i < 4; ++i)
+      snprintf(names[i], 32, "%s", i < S.passes.size() ? (S.passes[i].v ? S.passes[i].v->name : "copy_scale") : "");
+  if (split) {
+    split[0] = S.split[0];
+    split[1] = S.split[1];
+  }
+  return FFT_OK;
+}
+
+int fft_profile_enable(fft_plan_t p, int enable) {
+  if (!p) return FFT_ERR_INVALID_ARGUMENT;
+  for (hipEvent_t e : p->ev) hipEventDestroy(e);
+  p->ev.clear();
+  p->prof = false;
+  p->prof_pending = false;
+  const size_t npass = p->kind == 1 ? 1 : p->sched.passes.size();
+  p->prof_ms.assign(npass, 0.0);
+  p->prof_n.assign(npass, 0);
+  if (!enable) return FFT_OK;
+  p->ev.resize(2 * npass);
+  for (auto& e : p->ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return hip_fail(r);
+  }
+  p->prof = true;
+  return FFT_OK;
+}
+
+int fft_profile_collect(fft_plan_t p) {
+  if (!p) return FFT_ERR_INVALID_ARGUMENT;
+  if (!p->prof || !p->prof_pending) return FFT_OK;
+  for (size_t i = 0; i < p->prof_ms.size(); ++i) {
+    float ms = 0;
+    hipError_t r = hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]);
+    if (r != hipSuccess) return hip_fail(r);
+    p->prof_ms[i] += ms;
+    p->prof_n[i] += 1;
+  }
+  p->prof_pending = false;
+  return FFT_OK;
+}
+
+int fft_profile_read(fft_plan_t p, int pass, double* total_ms, int64_t* launches) {
+  if (!p || pass < 0 || pass >= (int)p->prof_ms.size()) return FFT_ERR_INVALID_ARGUMENT;
+  if (total_ms) *total_ms = p->prof_ms[pass];
+  if (launches) *launches = p->prof_n[pass];
+  return FFT_OK;
+}
+
+int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int direction,
+                     const char* schedule, fft_plan_t* out) {
+  if (!out) return FFT_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  if (!sizes || count < 1 || count > (1 << 24)) return FFT_ERR_INVALID_ARGUMENT;
+  if (direction != FFT_FORWARD && direction != FFT_INVERSE) return FFT_ERR_INVALID_ARGUMENT;
+  if (dtype != FFT_C64 && dtype != FFT_C16F && dtype != FFT_C16BF) return FFT_ERR_INVALID_ARGUMENT;
+  ManyOptions opt;
+  if (parse_many_schedule(schedule, &opt)) return FFT_ERR_INVALID_ARGUMENT;
+  const ManyVariant* var = nullptr;
+  for (int i = 0; i < many_variant_count(); ++i) {
+    const ManyVariant* v = many_variant(i);
+    if (v->dtype == dtype && v->P == opt.P && v->threads == opt.threads) var = v;
+  }
+  if (!var) return FFT_ERR_INVALID_ARGUMENT;
+  const int max_tile = std::min(kManyMaxLg, ilog2_64((int64_t)opt.threads * opt.P));
+  if (opt.pass2 < 1 || opt.pass2 > max_tile + 1) return FFT_ERR_INVALID_ARGUMENT;
+
+  std::vector<ManyXform> xf((size_t)count);
+  std::vector<int> lgs((size_t)count);
+  int64_t off = 0, points = 0, pass_points = 0;
+  double flops = 0;
+  int max_lg = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t n = sizes[i];
+    if (!pow2(n) || ilog2_64(n) > FFT_MAX_LOG2_1D) return FFT_ERR_UNSUPPORTED_SIZE;
+    const int lg = ilog2_64(n);
+    if (lg > 2 * max_tile) return FFT_ERR_UNSUPPORTED_SIZE;
+    lgs[i] = lg;
+    max_lg = std::max(max_lg, lg);
+    ManyXform& x = xf[i];
+    memset(&x, 0, sizeof(x));
+    x.off = off;
+    x.lg = lg;
+    const bool split = lg >= opt.pass2 || lg > max_tile;
+    if (split) {
+      x.lg1 = (lg + 1) / 2;
+      if (x.lg1 > max_tile) x.lg1 = max_tile;
+      const int lg2 = lg - x.lg1;
+      const int64_t N2 = (int64_t)1 << lg2;
+      const int wa = tile_lines(x.lg1, opt.P, opt.threads);
+      x.nA = (int32_t)((N2 + wa - 1) / wa);
+      pass_points += 2 * n;
+    } else {
+      x.lg1 = 0;
+      x.nA = 0;
+      pass_points += n;
+    }
+    off += n;
+    points += n;
+    flops += 5.0 * (double)n * (double)lg;
+  }
+  if (off > ((int64_t)1 << 40)) return FFT_ERR_UNSUPPORTED_SIZE;
+
+  // transform order: biggest first (stable), or as given
+  std::vector<int32_t> ids((size_t)count);
+  for (int64_t i = 0; i < count; ++i) ids[i] = (int32_t)i;
+  if (!opt.given_order)
+    std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) { return lgs[a] > lgs[b]; });
+
+  // items: all first-pass tiles, then one-pass tiles, then second-pass tiles
+  std::vector<ManyItem> items;
+  std::vector<int32_t> order;
+  bool has_split = false;
+  for (int32_t id : ids) {
+    const ManyXform& x = xf[id];
+    if (x.nA == 0) continue;
+    has_split = true;
+    for (int t = 0; t < x.nA; ++t) items.push_back({MANY_A, x.lg1, id, t});
+  }
+  {
+    // one-pass transforms grouped by length, W lines per tile
+    std::vector<std::vector<int32_t>> by_lg(max_tile + 1);
+    for (int32_t id : ids)
+      if (xf[id].nA == 0) by_lg[xf[id].lg].push_back(id);
+    std::vector<int> lg_order;
+    for (int lg = max_tile; lg >= 0; --lg) lg_order.push_back(lg);
+    if (opt.given_order) {
+      lg_order.clear();
+      std::vector<bool> seen(max_tile + 1, false);
+      for (int32_t id : ids)
+        if (xf[id].nA == 0 && !seen[xf[id].lg]) {
+          seen[xf[id].lg] = true;
+          lg_order.push_back(xf[id].lg);
+        }
+    }
+    for (int lg : lg_order) {
+      const auto& v = by_lg[lg];
+      const int W = tile_lines(lg, opt.P, opt.threads);
+      for (size_t j = 0; j < v.size(); j += W) {
+        const int g = (int)std::min<size_t>(W, v.size() - j);
+        items.push_back({MANY_SINGLE, lg, (int32_t)order.size(), g});
+        for (int k = 0; k < g; ++k) order.push_back(v[j + k]);
+      }
+    }
+  }
+  for (int32_t id : ids) {
+    const ManyXform& x = xf[id];
+    if (x.nA == 0) continue;
+    const int lg2 = x.lg - x.lg1;
+    const int64_t N1 = (int64_t)1 << x.lg1;
+    const int wb = tile_lines(lg2, opt.P, opt.threads);
+    const int nb = (int)((N1 + wb - 1) / wb);
+    for (int t = 0; t < nb; ++t) items.push_back({MANY_B, lg2, id, t});
+  }
+  if (items.size() > (size_t)INT32_MAX) return FFT_ERR_UNSUPPORTED_SIZE;
+
+  fft_plan_s* p = new (std::nothrow) fft_plan_s();
+  if (!p) return FFT_ERR_NO_MEMORY;
+  p->kind = 1;
+  p->dims = 1;
+  p->n[0] = count;
+  p->n[1] = 1;
+  p->batch = count;
+  p->dtype = dtype;
+  p->direction = direction;
+  p->scale = direction > 0 ? 0.0 : 1.0;  // per-transform default unless set
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e);
+  }
+  // twiddle tables: stage tables of every tile length, inter-pass per split length
+  TableBuild tb;
+  ManyPlan& mp = p->many;
+  std::vector<bool> used(max_tile + 1, false);
+  for (const ManyItem& it : items)
+    if (it.lg >= 1) used[it.lg] = true;
+  std::vector<int64_t> soff(kManyMaxLg + 1, 0);
+  for (int lg = 1; lg <= max_tile; ++lg)
+    if (used[lg]) soff[lg] = tb.add_stage_table(1 << lg, opt.P);
+  std::map<int, int64_t> inter;
+  for (int64_t i = 0; i < count; ++i) {
+    ManyXform& x = xf[i];
+    if (x.nA == 0) continue;
+    auto it = inter.find(x.lg);
+    if (it == inter.end()) {
+      const int64_t N = (int64_t)1 << x.lg;
+      const int64_t lo = tb.add((int64_t)1 << x.lg1, 0, N, 1);
+      tb.add((int64_t)1 << (x.lg - x.lg1), 0, N, (int64_t)1 << x.lg1);
+      it = inter.emplace(x.lg, lo).first;
+    }
+    x.tw_lo = it->second;
+  }
+  int rc = upload_tables(p, tb, max_lg >= kGpuTwiddleMinLog2);
+  if (rc) {
+    fft_destroy(p);
+    return rc;
+  }
+  auto upload = [&](void** dptr, const void* src, size_t bytes) -> int {
+    hipError_t r = hipMalloc(dptr, std::max<size_t>(bytes, 16));
+    if (r != hipSuccess) {
+      *dptr = nullptr;
+      return r == hipErrorOutOfMemory ? FFT_ERR_NO_MEMORY : hip_fail(r);
+    }
+    if (bytes) {
+      r = hipMemcpy(*dptr, src, bytes, hipMemcpyHostToDevice);
+      if (r != hipSuccess) return hip_fail(r);
+    }
+    return FFT_OK;
+  };
+  rc = upload((void**)&mp.d_items, items.data(), items.size() * sizeof(ManyItem));
+  if (!rc) rc = upload((void**)&mp.d_xf, xf.data(), xf.size() * sizeof(ManyXform));
+  if (!rc) rc = upload((void**)&mp.d_order, order.data(), order.size() * sizeof(int32_t));
+  if (rc) {
+    fft_destroy(p);
+    return rc;
+  }
+  mp.active = true;
+  mp.var = var;
+  mp.d_tw = p->d_tables;
+  mp.count = count;
+  mp.n_items = (int64_t)items.size();
+  mp.points = points;
+  mp.pass_points = pass_points;
+  mp.flops = flops;
+  mp.dtype = dtype;
+  mp.has_split = has_split;
+  mp.gpu_twiddles = p->gpu_twiddles;
+  ManyArgs& a = mp.args;
+  memset(&a, 0, sizeof(a));
+  a.items = mp.d_items;
+  a.xf = mp.d_xf;
+  a.order = mp.d_order;
+  a.tw = mp.d_tw;
+  for (int lg = 0; lg <= kManyMaxLg; ++lg) a.stage_off[lg] = soff[lg];
+  a.n_items = (int32_t)items.size();
+  a.n_xforms = (int32_t)count;
+  a.spin_limit = 1 << 26;
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (e != hipSuccess) {
+    fft_destroy(p);
+    return hip_fail(e);
+  }
+  const int per_cu = std::max(1, var->max_blocks_per_cu());
+  mp.grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * cus, mp.n_items));
+  rc = many_alloc_workspace(mp, &p->ws, &p->ws_bytes);
+  if (rc) {
+    fft_destroy(p);
+    return rc;
+  }
+  p->ws_owned = true;
+  *out = p;
+  return FFT_OK;
+}
+
+int fft_plan_many(const int64_t* sizes, int64_t count, int dtype, int direction, fft_plan_t* out) {
+  return fft_plan_many_ex(sizes, count, dtype, direction, nullptr, out);
+}
+
+int fft_many_watchdog(fft_plan_t p, int clear) {
+  if (!p || p->kind != 1 || !p->ws) return FFT_ERR_INVALID_ARGUMENT;
+  int32_t flag = 0;
+  hipError_t e = hipMemcpy(&flag, (int32_t*)p->ws + 2, sizeof(flag), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e);
+  if (flag && clear) {
+    int32_t z = 0;
+    e = hipMemcpy((int32_t*)p->ws + 2, &z, sizeof(z), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return flag ? FFT_ERR_WATCHDOG : FFT_OK;
+}
+
+int fft_many_set_spin_limit(fft_plan_t p, int32_t limit) {
+  if (!p || p->kind != 1 || limit < 1) return FFT_ERR_INVALID_ARGUMENT;
+  p->many.args.spin_limit = limit;
+  return FFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Batched transforms of uneven power-of-two lengths in one persistent launch.
+//
+// The paper synchronises its passes with kernel boundaries ("we call the
+// kernel function three times to make sure synchronization when we use
+// global memory", Sec. 2.3.3).  Here one launch of resident workgroups pulls
+// work items from a device queue instead; the boundary between the two passes
+// of a split transform becomes a per-transform completion counter that the
+// first-pass tiles release and the second-pass tiles acquire.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mfft {
+
+enum ManyKind { MANY_SINGLE = 0, MANY_A = 1, MANY_B = 2 };
+
+// One work item = one workgroup-sized tile.
+//   MANY_SINGLE: b lines of length 2^lg; line m is transform order[a + m]
+//   MANY_A:      first pass of transform a, tile b (columns b*W .. b*W+W-1)
+//   MANY_B:      second pass of transform a, tile b
+struct ManyItem {
+  int32_t kind, lg, a, b;
+};
+
+// One transform: length 2^lg at element offset `off` of the packed buffer;
+// split transforms use N1 = 2^lg1 (first pass) and N2 = 2^(lg - lg1), have
+// nA first-pass tiles, and read the inter-pass tables at tw_lo (2^lg1
+// entries W_N^j) and tw_lo + 2^lg1 (2^(lg-lg1) entries W_N^{j*N1}).
+struct ManyXform {
+  int64_t off;
+  int64_t tw_lo;
+  int32_t lg, lg1, nA, pad;
+};
+
+constexpr int kManyMaxLg = 12;  // longest single-tile length: 2^12 points
+
+struct ManyArgs {
+  const void* in;
+  void* out;
+  const ManyItem* items;
+  const ManyXform* xf;
+  const int32_t* order;
+  const float2* tw;                   // base of the plan's tables
+  int64_t stage_off[kManyMaxLg + 1];  // stage table of a 2^lg tile
+  int32_t n_items, n_xforms;
+  int32_t* ws;                        // [0] queue head, [1] exits, [2] watchdog, [3..] done
+  float scale;                        // used when use_scale != 0
+  int32_t use_scale;                  // 0: per-transform default (1 or 1/N)
+  int32_t inverse;
+  int32_t spin_limit;
+};
+
+constexpr int kManyWsHeader = 4;  // ints before the per-transform counters
+
+struct ManyVariant {
+  int dtype, P, threads;
+  hipError_t (*launch)(const ManyArgs&, int grid, hipStream_t);
+  int (*max_blocks_per_cu)();
+};
+
+// Compiled persistent-kernel variants (storage type x points per lane x
+// workgroup size).
+int many_variant_count();
+const ManyVariant* many_variant(int i);
+
+// Host-side plan state (owned by fft_plan_s).
+struct ManyPlan {
+  bool active = false;
+  const ManyVariant* var = nullptr;
+  ManyItem* d_items = nullptr;
+  ManyXform* d_xf = nullptr;
+  int32_t* d_order = nullptr;
+  float2* d_tw = nullptr;
+  ManyArgs args{};
+  int64_t count = 0, n_items = 0;
+  int64_t points = 0, pass_points = 0, packed_bytes = 0;
+  double flops = 0;
+  int grid = 0;
+  int dtype = 0;
+  bool has_split = false;
+  bool gpu_twiddles = false;
+};
+
+size_t many_workspace_bytes(const ManyPlan& mp);
+int many_alloc_workspace(const ManyPlan& mp, void** ws, size_t* bytes);
+hipError_t many_reset_workspace(const ManyPlan& mp, void* ws);
+hipError_t many_launch(const ManyPlan& mp, const void* in, void* out, void* ws, float scale,
+                       bool use_scale, bool inverse, hipStream_t s);
+void many_free(ManyPlan& mp);
+
+}  // namespace mfft

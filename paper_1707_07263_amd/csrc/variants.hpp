@@ -1,0 +1,68 @@
+// Registry of compiled kernel variants.  Each variant is one instantiation of
+// the strip-pass template (sub-transform length L, points per lane P, lines
+// per workgroup W, lane mappings, inter-pass twiddle on/off, storage type).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_device.hpp"
+
+namespace mfft {
+
+enum Role { ROLE_ROW = 0, ROLE_SPLIT_A = 1, ROLE_COL = 2 };
+enum Dtype { DT_C64 = 0, DT_C16F = 1, DT_C16BF = 2 };
+
+using LaunchFn = hipError_t (*)(const PassArgs&, hipStream_t);
+
+struct Variant {
+  const char* name;
+  int L, P, W, threads, role, dtype;
+  int lds_bytes;
+  int tw_entries;  // stage-table entries for this (L, P)
+  LaunchFn launch;
+};
+
+template <int L, int P, int W, int LOADM, int STOREM, bool TWID, typename TS>
+hipError_t launch_strip(const PassArgs& a, hipStream_t s) {
+  constexpr int NT = W * Sched<L, P>::T;
+  hipLaunchKernelGGL((k_strip<L, P, W, LOADM, STOREM, TWID, TS>), dim3((unsigned)a.total_tiles),
+                     dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename TS> struct DtOf;
+template <> struct DtOf<float2> { static constexpr int v = DT_C64; };
+template <> struct DtOf<__half2> { static constexpr int v = DT_C16F; };
+template <> struct DtOf<c16bf> { static constexpr int v = DT_C16BF; };
+
+template <int ROLE, int L, int P, int W, typename TS>
+Variant make_variant(const char* name) {
+  constexpr int LOADM = ROLE == ROLE_ROW ? 0 : 1;
+  constexpr int STOREM = ROLE == ROLE_COL ? 1 : 0;
+  constexpr bool TWID = ROLE == ROLE_SPLIT_A;
+  Variant v;
+  v.name = name;
+  v.L = L;
+  v.P = Sched<L, P>::PP;
+  v.W = W;
+  v.threads = W * Sched<L, P>::T;
+  v.role = ROLE;
+  v.dtype = DtOf<TS>::v;
+  v.lds_bytes = W * LdsLayout<L>::LS * (int)sizeof(float2);
+  v.tw_entries = Sched<L, P>::TW;
+  v.launch = &launch_strip<L, P, W, LOADM, STOREM, TWID, TS>;
+  return v;
+}
+
+// Each instantiation file appends its variants.
+void add_variants_c64_row(void (*add)(const Variant&));
+void add_variants_c64_a(void (*add)(const Variant&));
+void add_variants_c64_col(void (*add)(const Variant&));
+void add_variants_c16(void (*add)(const Variant&));
+
+// trivial length-1 / copy-scale kernel
+hipError_t launch_scale_copy(int dtype, const void* in, void* out, int64_t n, float scale,
+                             hipStream_t s);
+
+}  // namespace mfft

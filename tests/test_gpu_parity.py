@@ -1,0 +1,272 @@
+"""GPU vs FP64-oracle parity for the strided (non-batched-uneven) plans.
+
+Every case runs through the C ABI (fft_plan / fft_exec via ctypes) on seeded
+inputs and compares each transform with the oracle: rel-L2 <= 1e-6*log2(N)
+for the FP32 path.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1707_07263_amd import capi, workloads
+from gpu_helpers import rel_l2_rows, require_gpu, tol_fp32, to_gpu_c64
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+def run_c64(x, shape, inverse=False, schedule=None, scale=None, inplace=False, dev=None):
+    """Plan + exec through the C ABI; returns the numpy result."""
+    xt = to_gpu_c64(x, dev)
+    n_total = int(np.prod(shape))
+    batch = xt.numel() // n_total
+    direction = capi.FFT_INVERSE if inverse else capi.FFT_FORWARD
+    h = capi.fft_plan_ex(list(shape), batch, len(shape), capi.FFT_C64, direction, schedule)
+    try:
+        if scale is not None:
+            capi.fft_set_scale(h, scale)
+        out = xt if inplace else torch.empty_like(xt)
+        ws = None
+        if inplace:
+            need = capi.fft_workspace_size(h)
+            if need:
+                ws = torch.empty(need, dtype=torch.uint8, device=dev)
+                capi.fft_set_workspace(h, ws.data_ptr(), need)
+        stream = torch.cuda.current_stream().cuda_stream
+        capi.fft_exec(h, xt.data_ptr(), out.data_ptr(), stream)
+        torch.cuda.synchronize()
+        res = out.cpu().numpy()
+    finally:
+        capi.fft_destroy(h)
+    return res
+
+
+def check_1d(x, n, inverse, dev, schedule=None):
+    got = run_c64(x, [n], inverse=inverse, schedule=schedule, dev=dev)
+    ref = oracle.fft(np.asarray(x, np.complex64), inverse=inverse)
+    err = rel_l2_rows(got, ref, n)
+    assert err.max() <= tol_fp32(n), (n, inverse, float(err.max()))
+    return err
+
+
+@pytest.mark.parametrize("lg", range(0, 15))
+@pytest.mark.parametrize("inverse", [False, True])
+def test_single_pass_sizes(dev, lg, inverse):
+    # one-kernel sizes 2^0..2^14, ragged batch (not a multiple of the lines per workgroup)
+    n = 1 << lg
+    batch = 3 if n >= 4096 else 37
+    x = workloads.normal_batch(n, batch, seed=1000 + lg)
+    check_1d(x, n, inverse, dev)
+
+
+@pytest.mark.parametrize("lg", range(15, 21))
+@pytest.mark.parametrize("inverse", [False, True])
+def test_two_pass_sizes(dev, lg, inverse):
+    n = 1 << lg
+    x = workloads.normal_batch(n, 3, seed=2000 + lg)
+    check_1d(x, n, inverse, dev)
+
+
+@pytest.mark.parametrize("split", [4, 64, 128, 256, 512, 2048, 4096])
+def test_two_pass_all_splits(dev, split):
+    # N = 2^16 with every split N1 x N2 that the variants allow (also forced
+    # two-pass at N = 2^12 where one pass would do)
+    n = 1 << 16
+    if split == 4:
+        n, split = 1 << 12, 64
+    x = workloads.normal_batch(n, 2, seed=split)
+    check_1d(x, n, False, dev, schedule=f"split={split}")
+    check_1d(x, n, True, dev, schedule=f"split={split}")
+
+
+def test_config1_n1024(dev):
+    # 1-D N=1024, batch 1, complex64, re/im ~ U[-1,1] seed 0; tolerance 1e-5
+    x = workloads.uniform_1d(1024, 1, seed=0)
+    err = check_1d(x, 1024, False, dev)
+    assert err.max() <= 1e-5
+
+
+def test_config2_n2p20_forward_inverse(dev):
+    # N = 2^20, batch 16, N(0,1) seed 1: forward, then inverse of the GPU output
+    n, b = 1 << 20, 16
+    x = workloads.normal_batch(n, b, seed=1)
+    xc = x.astype(np.complex64)
+    fwd = run_c64(xc, [n], dev=dev)
+    ref = oracle.fft(xc)
+    e1 = rel_l2_rows(fwd, ref, n)
+    assert e1.max() <= 2.0e-5, float(e1.max())
+    inv = run_c64(fwd, [n], inverse=True, dev=dev)
+    ref_inv = oracle.ifft(fwd)
+    e2 = rel_l2_rows(inv, ref_inv, n)
+    assert e2.max() <= 2.0e-5, float(e2.max())
+    rt = rel_l2_rows(inv, xc, n)
+    assert rt.max() <= 4.0e-5, float(rt.max())
+    # a typical FP32 FFT error at this size is ~2e-7; report a regression early
+    assert e1.max() < 1e-6, float(e1.max())
+
+
+def test_config3_2d_4096_image(dev):
+    z = workloads.speckle_image(4096, 4096, seed=2)
+    zc = z.astype(np.complex64)
+    got = run_c64(zc, [4096, 4096], dev=dev)
+    ref = oracle.fft2(zc)
+    err = rel_l2_rows(got.reshape(1, -1), ref.reshape(1, -1), 4096 * 4096)
+    assert err.max() <= 2.4e-5, float(err.max())
+    assert err.max() < 1e-6, float(err.max())
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 64), (64, 1), (2, 8), (8, 2), (16, 1024), (1024, 16),
+                                   (256, 512), (512, 256), (4096, 8), (8, 4096), (128, 16384),
+                                   (16384, 4)])
+@pytest.mark.parametrize("inverse", [False, True])
+def test_2d_shapes(dev, shape, inverse):
+    r, c = shape
+    b = 2
+    x = workloads.normal_batch(r * c, b, seed=r * 7 + c).reshape(b, r, c)
+    got = run_c64(x, [r, c], inverse=inverse, dev=dev)
+    ref = oracle.fft2(x.astype(np.complex64), inverse=inverse)
+    err = rel_l2_rows(got.reshape(b, -1), ref.reshape(b, -1), r * c)
+    assert err.max() <= tol_fp32(r * c), (shape, float(err.max()))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("lg", [22, 24])
+def test_gpu_fp64_twiddles_large(dev, lg):
+    # 1-D N >= 2^22: tables are generated on the GPU in FP64
+    n = 1 << lg
+    x = workloads.normal_batch(n, 1, seed=5)
+    h = capi.fft_plan([n], 1, 1, capi.FFT_C64, capi.FFT_FORWARD)
+    try:
+        assert capi.fft_plan_info(h)["gpu_twiddles"] == 1
+    finally:
+        capi.fft_destroy(h)
+    check_1d(x, n, False, dev)
+    check_1d(x, n, True, dev)
+
+
+def test_closed_forms_on_gpu(dev):
+    for n in (16, 1024, 1 << 16):
+        k = np.arange(n)
+        x = np.zeros((3, n), complex)
+        x[0, 0] = 1.0                        # impulse -> all ones
+        x[1, :] = 0.5                        # constant -> N/2 at k = 0
+        k0 = n // 3
+        x[2, :] = np.exp(2j * np.pi * ((k0 * k) % n) / n)  # tone -> N at k0
+        got = run_c64(x, [n], dev=dev)
+        assert np.max(np.abs(got[0] - 1.0)) < 1e-6
+        want1 = np.zeros(n)
+        want1[0] = n / 2
+        assert np.max(np.abs(got[1] - want1)) < 1e-6 * n
+        want2 = np.zeros(n, complex)
+        want2[k0] = n
+        assert np.max(np.abs(got[2] - want2)) < 2e-6 * n
+
+
+def test_impulse_batch_is_dft_matrix(dev):
+    for n in (2, 8, 64, 256):
+        eye = np.eye(n, dtype=complex)
+        got = run_c64(eye, [n], dev=dev)
+        j, k = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        want = np.exp(-2j * np.pi * ((j * k) % n) / n)
+        assert np.max(np.abs(got - want)) < 2e-6
+
+
+@pytest.mark.parametrize("n", [1024, 1 << 18])
+def test_inplace(dev, n):
+    x = workloads.normal_batch(n, 4, seed=9)
+    got = run_c64(x, [n], inplace=True, dev=dev)
+    ref = oracle.fft(x.astype(np.complex64))
+    assert rel_l2_rows(got, ref, n).max() <= tol_fp32(n)
+    got2 = run_c64(x.reshape(4, 32, n // 32), [32, n // 32], inplace=True, dev=dev)
+    ref2 = oracle.fft2(x.astype(np.complex64).reshape(4, 32, n // 32))
+    assert rel_l2_rows(got2.reshape(4, -1), ref2.reshape(4, -1), n).max() <= tol_fp32(n)
+
+
+def test_scale_override_and_adjoint(dev):
+    n = 1 << 16
+    x = workloads.normal_batch(n, 2, seed=11).astype(np.complex64)
+    y = workloads.normal_batch(n, 2, seed=12).astype(np.complex64)
+    adj = run_c64(y, [n], inverse=True, scale=1.0, dev=dev)
+    ref = oracle.adjoint(y)
+    assert rel_l2_rows(adj, ref, n).max() <= tol_fp32(n)
+    fx = run_c64(x, [n], dev=dev)
+    # dot-product test <F x, y> = <x, F^H y>
+    lhs = np.vdot(y.astype(np.complex128), fx.astype(np.complex128))
+    rhs = np.vdot(adj.astype(np.complex128), x.astype(np.complex128))
+    bound = 1e-6 * math.log2(n) * np.linalg.norm(fx) * np.linalg.norm(y)
+    assert abs(lhs - rhs) <= bound
+    half = run_c64(x, [n], scale=0.5, dev=dev)
+    assert rel_l2_rows(half, 0.5 * oracle.fft(x), n).max() <= tol_fp32(n)
+
+
+def test_deterministic_repeats(dev):
+    n = 1 << 20
+    x = to_gpu_c64(workloads.normal_batch(n, 2, seed=13), dev)
+    h = capi.fft_plan([n], 2, 1, capi.FFT_C64, capi.FFT_FORWARD)
+    try:
+        outs = []
+        for _ in range(3):
+            o = torch.empty_like(x)
+            capi.fft_exec(h, x.data_ptr(), o.data_ptr(), torch.cuda.current_stream().cuda_stream)
+            outs.append(o)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    finally:
+        capi.fft_destroy(h)
+
+
+def test_other_stream(dev):
+    n = 4096
+    x = workloads.normal_batch(n, 8, seed=14)
+    xt = to_gpu_c64(x, dev)
+    s = torch.cuda.Stream()
+    out = torch.empty_like(xt)
+    torch.cuda.synchronize()
+    h = capi.fft_plan([n], 8, 1, capi.FFT_C64, capi.FFT_FORWARD)
+    try:
+        with torch.cuda.stream(s):
+            capi.fft_exec(h, xt.data_ptr(), out.data_ptr(), s.cuda_stream)
+        s.synchronize()
+    finally:
+        capi.fft_destroy(h)
+    assert rel_l2_rows(out.cpu().numpy(), oracle.fft(x.astype(np.complex64)), n).max() <= tol_fp32(n)
+
+
+def test_error_codes(dev):
+    n = 1 << 18
+    x = torch.zeros(2 * n + 1, dtype=torch.complex64, device=dev)
+    h = capi.fft_plan([n], 2, 1, capi.FFT_C64, capi.FFT_FORWARD)
+    try:
+        # misaligned pointer (4 bytes off an 8-byte element)
+        st = capi.fft_exec_status(h, x.data_ptr() + 4, x.data_ptr(), 0)
+        assert st == capi.FFT_ERR_ALIGNMENT
+        # in place on a two-pass plan without a workspace
+        assert capi.fft_exec_status(h, x.data_ptr(), x.data_ptr(), 0) == capi.FFT_ERR_INPLACE
+        # partial overlap
+        assert capi.fft_exec_status(h, x.data_ptr(), x.data_ptr() + 8, 0) == capi.FFT_ERR_INPLACE
+        assert capi.fft_exec_status(h, 0, x.data_ptr(), 0) == capi.FFT_ERR_INVALID_ARGUMENT
+    finally:
+        capi.fft_destroy(h)
+    for bad, code in (([12], capi.FFT_ERR_UNSUPPORTED_SIZE), ([1 << 25], capi.FFT_ERR_UNSUPPORTED_SIZE),
+                      ([0], capi.FFT_ERR_UNSUPPORTED_SIZE)):
+        with pytest.raises(capi.FFTError) as ei:
+            capi.fft_plan(bad, 1, 1, capi.FFT_C64, capi.FFT_FORWARD)
+        assert ei.value.status == code
+    with pytest.raises(capi.FFTError) as ei:
+        capi.fft_plan([16], 1, 1, 7, capi.FFT_FORWARD)
+    assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT
+    with pytest.raises(capi.FFTError) as ei:
+        capi.fft_plan([16], 1, 1, capi.FFT_C64, 0)
+    assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT
+    with pytest.raises(capi.FFTError) as ei:
+        capi.fft_plan_ex([1 << 16], 1, 1, capi.FFT_C64, -1, "a=nonexistent")
+    assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT
+    capi.fft_destroy(0)  # NULL is a no-op
