@@ -1,0 +1,322 @@
+#!/usr/bin/env python3
+"""Benchmark of the FFT hot path on one MI355X.
+
+Workload (one "step"): the 1-D complex-to-complex FFT of 16 signals of
+N = 2^20 points (complex64, re/im ~ N(0,1), seed 1), forward then inverse.
+N = 2^20 exceeds one workgroup's LDS, so each direction is the two-pass
+N1 x N2 = 1024 x 1024 split (pass A: 1024-point column transforms with the
+fused W_N^{n2*k1} twiddle; pass B: 1024-point column transforms).
+
+metric  GFLOP/s = sum over transforms of 5*N*log2(N) / step time.
+roofline  the dominant kernel's algorithmic bytes per launch (every point
+          read once and written once: 2 * 16 * 2^20 * 8 B) over its average
+          launch time, timed live with HIP events recorded by the library on
+          the exec stream, against MI355X peak HBM (8 TB/s).
+cpu_baseline  the FP64 oracle on the host's cores on a bounded sample of the
+          same step.
+
+Buffers rotate over >= 1 GiB so that the 256 MB Infinity Cache cannot hold a
+step's working set between steps: every step reads its input from HBM.
+
+Other modes (used to make the rocprofv3 summaries under profiles/):
+  --mode profile     run warmup + steps only (no CPU baseline), for
+                     `rocprofv3 --kernel-trace --stats` and `--pmc` runs;
+                     also runs one plain 256 MiB device copy (calibration).
+  --summarize-trace DIR         print the kernel-time summary of a trace run
+  --summarize-pmc DIR_FETCH DIR_WRITE  print per-kernel HBM traffic
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N = 1 << 20
+BATCH = 16
+SEED = 1
+PEAK_HBM_GBS = 8000.0
+ROT_BYTES = 1 << 30
+COPY_BYTES = 256 << 20
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_fft_n2p20_b16.txt")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the device sources; a traffic figure is only valid for the
+    kernels it was measured on."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1707_07263_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hpp", ".hip", ".cpp", ".py")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse_args(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--mode", choices=["bench", "profile"], default="bench")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--summarize-trace", metavar="DIR")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("DIR_FETCH", "DIR_WRITE"))
+    return ap.parse_args(argv)
+
+
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries
+# ---------------------------------------------------------------------------
+def _csv_rows(root, suffix):
+    rows = []
+    for path in glob.glob(os.path.join(root, "**", "*" + suffix), recursive=True):
+        with open(path, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def _short(name: str) -> str:
+    name = name.strip()
+    for key in ("k_strip", "k_many", "k_scale_copy", "k_twiddle_fp64"):
+        if key in name:
+            return name
+    return name[:120]
+
+
+def summarize_trace(d: str) -> str:
+    rows = _csv_rows(d, "kernel_stats.csv")
+    if not rows:
+        raise SystemExit(f"no kernel_stats.csv under {d}")
+    lines = ["kernel | calls | avg_us | total_ms | pct"]
+    for r in sorted(rows, key=lambda r: -float(r.get("TotalDurationNs", 0))):
+        calls = int(r["Calls"])
+        avg = float(r["AverageNs"]) / 1e3
+        tot = float(r["TotalDurationNs"]) / 1e6
+        pct = float(r.get("Percentage", 0))
+        lines.append(f"{_short(r['Name'])} | {calls} | {avg:.2f} | {tot:.3f} | {pct:.2f}")
+    return "\n".join(lines)
+
+
+def _pmc_per_kernel(d: str, counter: str):
+    rows = _csv_rows(d, "counter_collection.csv")
+    per = {}
+    for r in rows:
+        if r.get("Counter_Name", "").strip() != counter:
+            continue
+        k = _short(r["Kernel_Name"])
+        per.setdefault(k, []).append(float(r["Counter_Value"]))
+    return per
+
+
+def summarize_pmc(dfetch: str, dwrite: str) -> str:
+    fetch = _pmc_per_kernel(dfetch, "FETCH_SIZE")
+    write = _pmc_per_kernel(dwrite, "WRITE_SIZE")
+    copy_f = [v for k, vs in fetch.items() if "copy" in k.lower() or "elementwise" in k.lower() for v in vs]
+    copy_w = [v for k, vs in write.items() if "copy" in k.lower() or "elementwise" in k.lower() for v in vs]
+    lines = [f"source_hash={kernel_source_hash()}"]
+    if copy_f and copy_w:
+        kib = COPY_BYTES / 1024.0
+        cf = kib / max(copy_f)
+        cw = kib / max(copy_w)
+        lines.append(f"copy_calibration fetch_kib={max(copy_f):.1f} write_kib={max(copy_w):.1f} "
+                     f"expected_kib={kib:.1f} fetch_scale={cf:.4f} write_scale={cw:.4f}")
+    else:
+        cf = cw = 1.0
+        lines.append("copy_calibration missing fetch_scale=1 write_scale=1")
+    for k in sorted(set(fetch) | set(write)):
+        f = fetch.get(k, [])
+        w = write.get(k, [])
+        if not f or not w:
+            continue
+        af = sum(f) / len(f)
+        aw = sum(w) / len(w)
+        lines.append(f"kernel={k} dispatches={len(f)} fetch_kib_avg={af:.1f} write_kib_avg={aw:.1f} "
+                     f"hbm_bytes_per_launch={(af * cf + aw * cw) * 1024:.0f}")
+    return "\n".join(lines)
+
+
+def read_traffic(kernel_name: str):
+    """Scaled HBM bytes per launch of `kernel_name` from the committed pmc
+    summary, or None if absent or measured on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        text = f.read().splitlines()
+    kv = [l for l in text if l.startswith("source_hash=")]
+    if not kv or kv[0].split("=", 1)[1].strip() != kernel_source_hash():
+        return None
+    for line in text:
+        if line.startswith("kernel=") and kernel_name in line:
+            for tok in line.split():
+                if tok.startswith("hbm_bytes_per_launch="):
+                    return float(tok.split("=", 1)[1])
+    return None
+
+
+# ---------------------------------------------------------------------------
+# GPU benchmark
+# ---------------------------------------------------------------------------
+def cpu_baseline(x_np, seconds: float):
+    """FP64 oracle on the host cores: forward + inverse of the same 16 x 2^20
+    batch, repeated until `seconds` have passed (at least once)."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    oracle.set_threads(cores)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        y = oracle.fft(x_np)
+        oracle.fft(y, inverse=True)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or reps >= 100:
+            break
+    flops = reps * 2 * BATCH * 5.0 * N * math.log2(N)
+    return {"value": round(flops / el / 1e9, 3), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"{reps} x (forward + inverse of 16 x 2^20 complex, FP64 radix-2) in {el:.1f} s"}
+
+
+def main(argv=None) -> int:
+    args = parse_args(argv)
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
+        return 0
+    if args.summarize_pmc:
+        print(summarize_pmc(*args.summarize_pmc))
+        return 0
+    if args.gpus != 1:
+        print("bench.py: this build targets one GPU; --gpus N > 1 is not supported. The batch of "
+              "independent transforms would shard by rows with no communication.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1707_07263_amd import capi, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    capi.load()
+    print(f"[bench] generating 16 x 2^20 complex64 input (seed {SEED})", file=sys.stderr, flush=True)
+    x_np = workloads.normal_batch(N, BATCH, seed=SEED).astype(np.complex64)
+    x = torch.from_numpy(x_np).to(dev)
+    set_bytes = 3 * x.numel() * 8
+    nsets = max(1, math.ceil(ROT_BYTES / set_bytes))
+    sets = []
+    for _ in range(nsets):
+        sets.append((x.clone(), torch.empty_like(x), torch.empty_like(x)))
+    del x
+    fwd = capi.fft_plan([N], BATCH, 1, capi.FFT_C64, capi.FFT_FORWARD)
+    inv = capi.fft_plan([N], BATCH, 1, capi.FFT_C64, capi.FFT_INVERSE)
+    info_f = capi.fft_plan_info(fwd)
+    info_i = capi.fft_plan_info(inv)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def step(i):
+        xi, yi, zi = sets[i % nsets]
+        capi.fft_exec(fwd, xi.data_ptr(), yi.data_ptr(), stream)
+        capi.fft_exec(inv, yi.data_ptr(), zi.data_ptr(), stream)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    if args.mode == "profile":
+        for i in range(args.steps):
+            step(i)
+        torch.cuda.synchronize()
+        a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] profile mode: {args.steps} steps + one {COPY_BYTES >> 20} MiB copy", file=sys.stderr)
+        return 0
+
+    capi.fft_profile_enable(fwd, args.steps)
+    capi.fft_profile_enable(inv, args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    capi.fft_profile_collect(fwd)
+    capi.fft_profile_collect(inv)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.4f} ms/step", file=sys.stderr, flush=True)
+
+    # per-kernel launch times from the library's HIP events
+    kernels = []
+    for plan, info, dname in ((fwd, info_f, "forward"), (inv, info_i, "inverse")):
+        for p in range(info["passes"]):
+            ms, cnt = capi.fft_profile_read(plan, p)
+            kernels.append({"direction": dname, "pass": p, "variant": info["pass_variant"][p],
+                            "avg_us": 1e3 * ms / max(cnt, 1), "launches": cnt,
+                            "bytes": info["bytes_pass"][p], "total_ms": ms})
+    dom = max(kernels, key=lambda k: k["total_ms"])
+    achieved = dom["bytes"] / (dom["avg_us"] * 1e-6) / 1e9
+    traffic = read_traffic(dom["variant"])
+
+    # round trip of the last step's buffers as a sanity check
+    xi, yi, zi = sets[(args.warmup + args.steps - 1) % nsets]
+    rt = (torch.linalg.vector_norm(zi - xi) / torch.linalg.vector_norm(xi)).item()
+
+    flops_step = info_f["flops"] + info_i["flops"]
+    value = flops_step / (ms_per_step * 1e-3) / 1e9
+    result = {
+        "metric": "GFLOP/s (5N log2N/t), 1-D C2C FFT forward+inverse",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1-D C2C FFT forward then inverse, N=2^20 (four-step 1024x1024), "
+                               "batch 16, complex64, N(0,1) seed 1",
+                   "n": N, "batch": BATCH, "passes_per_direction": info_f["passes"],
+                   "hbm_bytes_moved_per_step": 2 * sum(info_f["bytes_pass"]),
+                   "effective_GBps": round(2 * sum(info_f["bytes_pass"]) / (ms_per_step * 1e-3) / 1e9, 1),
+                   "rotating_sets": nsets, "round_trip_rel_l2": rt},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "kernel": dom["variant"], "kernel_avg_us": round(dom["avg_us"], 3),
+                     "kernel_bytes_per_launch": dom["bytes"],
+                     "kernels": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in kk.items()}
+                                 for kk in kernels]},
+    }
+    capi.fft_destroy(fwd)
+    capi.fft_destroy(inv)
+    del sets
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(x_np, args.cpu_seconds)
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

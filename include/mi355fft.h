@@ -112,7 +112,8 @@ int fft_plan_many(const int64_t *sizes, int64_t count, int dtype, int direction,
  * As fft_plan_many with a schedule string of ';'-separated items:
  *   'p=' 8|16          points per lane (radix of the in-register stages)
  *   'threads=' 256|512 workgroup size (not every dtype has every size)
- *   'pass2=' t         lengths of at least 2^t use two passes (1 <= t <= 13)
+ *   'pass2=' t         lengths of at least 2^t use two passes (1 <= t <= 1 +
+ *                      log2 of the longest one-tile length, which is the default)
  *   'order=' bigfirst|given   order of the work queue
  * FFT_ERR_INVALID_ARGUMENT for a malformed item or an uncompiled combination.
  * In-place exec (in == out) is refused with FFT_ERR_INPLACE when any length
@@ -122,14 +123,29 @@ int fft_plan_many_ex(const int64_t *sizes, int64_t count, int dtype, int directi
                      const char *schedule, fft_plan_t *out);
 
 /*
- * Batched plans only: the second-pass tiles wait on a counter with a bounded
- * spin.  fft_many_watchdog() reads (blocking) the flag the kernel sets when a
- * wait expired, returning FFT_ERR_WATCHDOG if set (and clearing it if
- * `clear`); fft_many_set_spin_limit() sets the bound (in sleep-polls,
- * default 2^26).  An expired wait means the results are invalid.
+ * Host-only view of the work queue fft_plan_many_ex would build (no GPU use):
+ * *n_items items; if `items` is not NULL it receives 4 ints per item in queue
+ * order: kind (0 one-pass tile, 1 first-pass tile, 2 second-pass tile),
+ * log2 of the tile's transform length, transform index (for a one-pass tile:
+ * its first transform), and the tile number (one-pass: the number of
+ * transforms in the tile).  first_len[i] / first_tiles[i] (each may be NULL)
+ * receive N1 and the first-pass tile count of transform i (0 for one-pass
+ * transforms).  FFT_ERR_INVALID_ARGUMENT if max_items is too small.
+ */
+int fft_describe_many(const int64_t *sizes, int64_t count, int dtype, const char *schedule,
+                      int32_t *items, int64_t max_items, int64_t *n_items, int32_t *first_len,
+                      int32_t *first_tiles);
+
+/*
+ * Batched plans only: a second-pass tile waits on its transform's counter for
+ * at most a wall-clock bound (default 2 s per wait), then sets a watchdog
+ * flag and goes on, so the kernel always finishes.  fft_many_watchdog()
+ * reads (blocking) that flag, returning FFT_ERR_WATCHDOG if set (and clearing
+ * it if `clear`); an expired wait means the results are invalid.
+ * fft_many_set_wait_limit() sets the bound in microseconds (1 .. 2^40).
  */
 int fft_many_watchdog(fft_plan_t plan, int clear);
-int fft_many_set_spin_limit(fft_plan_t plan, int32_t limit);
+int fft_many_set_wait_limit(fft_plan_t plan, int64_t microseconds);
 
 /*
  * Queue the transform on `stream`.  Asynchronous: no host synchronisation, no
@@ -206,16 +222,28 @@ int fft_describe(const int64_t *n, int64_t batch, int dims, int dtype,
 
 /*
  * Per-launch timing with HIP events recorded on the exec stream around each
- * kernel.  fft_profile_enable(plan, 1) creates the events (blocking) and
- * clears the totals; afterwards every fft_exec records them.  After the
- * caller has synchronised the stream, fft_profile_collect() adds the elapsed
- * time of the last exec's launches to running totals, and
+ * kernel.  fft_profile_enable(plan, slots) with slots >= 1 creates events for
+ * `slots` execs (blocking) and clears the totals; every later fft_exec
+ * records its launches into the next slot (a ring: execs beyond `slots`
+ * between two collects overwrite the oldest).  slots = 0 turns timing off.
+ * After the caller has synchronised the stream, fft_profile_collect() adds
+ * the elapsed time of every pending exec's launches to running totals, and
  * fft_profile_read(plan, pass, &ms, &count) returns the total milliseconds
- * and the number of launches of pass `pass`.
+ * and the number of timed launches of pass `pass` (0-based launch index
+ * within one exec).
  */
-int fft_profile_enable(fft_plan_t plan, int enable);
+int fft_profile_enable(fft_plan_t plan, int slots);
 int fft_profile_collect(fft_plan_t plan);
 int fft_profile_read(fft_plan_t plan, int pass, double *total_ms, int64_t *launches);
+
+/*
+ * The host twiddle generator, for inspection and tests: writes `count`
+ * float32 pairs out[2i], out[2i+1] = W_M^{e(i)} (re, im) with
+ * e(i) = (i / R) * (i % R) * mul for R > 0 and e(i) = i * mul for R == 0,
+ * each the float64 value of Sec. 2.3.1's sin/cos table rounded to nearest.
+ * M must be a power of two.  Host memory; no GPU use.
+ */
+int fft_twiddle_host(int64_t count, int64_t R, int64_t M, int64_t mul, float *out);
 
 #ifdef __cplusplus
 }

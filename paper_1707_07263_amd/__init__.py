@@ -17,11 +17,10 @@ __all__ = ["capi", "workloads", "fft", "ifft", "fft2", "ifft2", "fft_many", "FFT
 def __getattr__(name):
     # torch-facing helpers load lazily so that importing the package (for the
     # input generators, say) does not touch the GPU library
+    import importlib
+    if name in ("api", "autotune"):
+        return importlib.import_module(f"{__name__}.{name}")
     if name in ("fft", "ifft", "fft2", "ifft2", "fft_many", "FFTFunction", "fft_autograd",
-                "get_plan", "get_many_plan", "api", "clear_cache", "variants"):
-        from . import api
-        return api if name == "api" else getattr(api, name)
-    if name == "autotune":
-        from . import autotune
-        return autotune
+                "get_plan", "get_many_plan", "clear_cache", "variants"):
+        return getattr(importlib.import_module(f"{__name__}.api"), name)
     raise AttributeError(name)

@@ -29,10 +29,11 @@ FFT_ERR_WATCHDOG = -7
 
 EXPORTED = (
     "fft_plan", "fft_plan_ex", "fft_plan_many", "fft_plan_many_ex", "fft_many_watchdog",
-    "fft_many_set_spin_limit", "fft_exec", "fft_set_scale", "fft_workspace_size",
+    "fft_many_set_wait_limit", "fft_exec", "fft_set_scale", "fft_workspace_size",
     "fft_set_workspace", "fft_plan_info", "fft_destroy", "fft_error_string",
     "fft_last_hip_error", "fft_variant_count", "fft_variant_name", "fft_variant_describe",
     "fft_describe", "fft_profile_enable", "fft_profile_collect", "fft_profile_read",
+    "fft_twiddle_host", "fft_describe_many",
 )
 
 
@@ -92,7 +93,7 @@ def load():
         "fft_plan_many_ex": ([i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, pp],
                              ctypes.c_int),
         "fft_many_watchdog": ([vp, ctypes.c_int], ctypes.c_int),
-        "fft_many_set_spin_limit": ([vp, ctypes.c_int32], ctypes.c_int),
+        "fft_many_set_wait_limit": ([vp, ctypes.c_int32], ctypes.c_int),
         "fft_exec": ([vp, vp, vp, vp], ctypes.c_int),
         "fft_set_scale": ([vp, ctypes.c_double], ctypes.c_int),
         "fft_workspace_size": ([vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -110,6 +111,12 @@ def load():
         "fft_profile_enable": ([vp, ctypes.c_int], ctypes.c_int),
         "fft_profile_collect": ([vp], ctypes.c_int),
         "fft_profile_read": ([vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), i64p], ctypes.c_int),
+        "fft_describe_many": ([i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_char_p,
+                               ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, i64p,
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+                              ctypes.c_int),
+        "fft_twiddle_host": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                              ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -172,8 +179,8 @@ def fft_many_watchdog(plan: int, clear: bool = True) -> int:
     return rc
 
 
-def fft_many_set_spin_limit(plan: int, limit: int) -> None:
-    _check(load().fft_many_set_spin_limit(plan, int(limit)), "fft_many_set_spin_limit")
+def fft_many_set_wait_limit(plan: int, microseconds: int) -> None:
+    _check(load().fft_many_set_wait_limit(plan, int(microseconds)), "fft_many_set_wait_limit")
 
 
 def fft_exec(plan: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
@@ -248,8 +255,9 @@ def fft_describe(n, batch, dims, dtype, schedule=None) -> dict:
             "split": [split[0], split[1]]}
 
 
-def fft_profile_enable(plan: int, enable: bool = True) -> None:
-    _check(load().fft_profile_enable(plan, 1 if enable else 0), "fft_profile_enable")
+def fft_profile_enable(plan: int, slots: int = 1) -> None:
+    """Time the next `slots` execs per launch with HIP events (0: off)."""
+    _check(load().fft_profile_enable(plan, int(slots)), "fft_profile_enable")
 
 
 def fft_profile_collect(plan: int) -> None:
@@ -262,3 +270,31 @@ def fft_profile_read(plan: int, pass_index: int):
     _check(load().fft_profile_read(plan, int(pass_index), ctypes.byref(ms), ctypes.byref(n)),
            "fft_profile_read")
     return ms.value, n.value
+
+
+def fft_twiddle_host(count: int, R: int, M: int, mul: int = 1):
+    """Host twiddle table entries W_M^{e(i)} as a complex64 numpy array."""
+    import numpy as np
+    out = np.empty(2 * int(count), dtype=np.float32)
+    _check(load().fft_twiddle_host(int(count), int(R), int(M), int(mul),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+           "fft_twiddle_host")
+    return out[0::2] + 1j * out[1::2].astype(np.complex64)
+
+
+def fft_describe_many(sizes, dtype=FFT_C64, schedule=None):
+    """Host-only work queue of a batched plan: (items [n, 4], first_len, first_tiles)."""
+    import numpy as np
+    lib = load()
+    sz = _i64(sizes)
+    n = ctypes.c_int64()
+    _check(lib.fft_describe_many(sz, len(sizes), int(dtype), _sched(schedule), None, 0,
+                                 ctypes.byref(n), None, None), "fft_describe_many")
+    items = np.zeros((n.value, 4), dtype=np.int32)
+    fl = np.zeros(len(sizes), dtype=np.int32)
+    ft = np.zeros(len(sizes), dtype=np.int32)
+    p32 = ctypes.POINTER(ctypes.c_int32)
+    _check(lib.fft_describe_many(sz, len(sizes), int(dtype), _sched(schedule),
+                                 items.ctypes.data_as(p32), n.value, ctypes.byref(n),
+                                 fl.ctypes.data_as(p32), ft.ctypes.data_as(p32)), "fft_describe_many")
+    return items, fl, ft

@@ -193,6 +193,7 @@ struct PassArgs {
   const float2* tw;             // stage table of this (L, P)
   const float2* tw_lo;          // inter-pass: W_N^{j & mask}
   const float2* tw_hi;          // inter-pass: W_N^{(j >> shift) << shift}
+  const float2* tw_step;        // inter-pass: W_N^{line*q*T}, [lines][P]
   int32_t tw_shift, tw_mask;
   float scale;                  // applied to every output value
   int32_t conj_in, conj_out;    // inverse direction: conj on first load / last store
@@ -207,6 +208,52 @@ __device__ __forceinline__ int64_t tile_of(int64_t b, int64_t n, int remap) {
 }
 
 // ---------------------------------------------------------------------------
+// LDS exchange between two stages.  Lane (m, t) holds the previous stage's
+// outputs in v[b + r*NB] destined for positions o0[b] + r*NS of line m; after
+// the exchange lane (m2, t2) holds points t2 + q*T of line m2 in v[q].
+// EX = 0 moves (re, im) pairs in one round through a float2 array; EX = 1
+// moves the real parts, then the imaginary parts, through a float array of
+// half the size (twice the barriers, half the LDS, so twice the workgroups
+// fit on a CU).
+// ---------------------------------------------------------------------------
+template <int L, int PP, int EX, int R, int NS>
+__device__ __forceinline__ void exchange(float2* v, void* ldsv, int m, int m2, int t2, const int* o0) {
+  using LY = LdsLayout<L>;
+  constexpr int T = L / PP;
+  constexpr int NB = PP / R;
+  if constexpr (EX == 0) {
+    float2* lds = reinterpret_cast<float2*>(ldsv);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[LY::idx(m, o0[b] + r * NS)] = v[b + r * NB];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PP; ++q) v[q] = lds[LY::idx(m2, t2 + q * T)];
+    __syncthreads();
+  } else {
+    float* lds = reinterpret_cast<float*>(ldsv);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[LY::idx(m, o0[b] + r * NS)] = v[b + r * NB].x;
+    __syncthreads();
+    // the real parts are dead once written: reuse their registers
+#pragma unroll
+    for (int q = 0; q < PP; ++q) v[q].x = lds[LY::idx(m2, t2 + q * T)];
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[LY::idx(m, o0[b] + r * NS)] = v[b + r * NB].y;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PP; ++q) v[q].y = lds[LY::idx(m2, t2 + q * T)];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The engine: all stages of W independent L-point transforms held by one
 // workgroup, P points per lane.  On entry lane (m, t) holds points t + q*T of
 // line m in v[q]; on exit lane (m_st, t_st) holds outputs t_st + q*T of line
@@ -215,70 +262,65 @@ __device__ __forceinline__ int64_t tile_of(int64_t b, int64_t n, int remap) {
 // j + r*L/R, multiplies them by W_{NS*R}^{(j mod NS)*r}, runs an R-point DFT
 // and writes output r to (j div NS)*NS*R + (j mod NS) + r*NS.  The lane
 // mapping switches from (m, t) to (m_st, t_st) at the first LDS exchange.
+// Stages are unrolled by compile-time recursion so that every radix, span
+// and register index is a constant.
 // ---------------------------------------------------------------------------
-template <int L, int P, int W>
-__device__ __forceinline__ void run_stages(float2* v, float2* lds, int& m, int& t,
-                                           int m_st, int t_st, bool remap,
-                                           const float2* __restrict__ twt) {
+template <int L, int P, int EX, int s>
+struct Stage {
   using S = Sched<L, P>;
-  using LY = LdsLayout<L>;
-  constexpr int T = S::T;
-  constexpr int PP = S::PP;
-#pragma unroll
-  for (int s = 0; s < S::S; ++s) {
-    const int R = S::radix(s);
-    const int NS = S::ns(s);
-    const int NB = PP / R;
-    const bool last = (s == S::S - 1);
+  static constexpr int T = S::T;
+  static constexpr int PP = S::PP;
+  static constexpr int R = S::radix(s);
+  static constexpr int NS = S::ns(s);
+  static constexpr int NB = PP / R;
+  __device__ __forceinline__ static void run(float2* v, void* lds, int& m, int& t, int m_st,
+                                             int t_st, const float2* __restrict__ twt) {
+    int o0[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int j = t + b * T;
       const int k = j & (NS - 1);
-      float2 x[PP];
+      o0[b] = (j / NS) * NS * R + k;
+      float2 x[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) x[r] = v[b + r * NB];
-      if (s > 0) {
+      if constexpr (s > 0) {
         const float2* tw = twt + S::off(s) + k * R;
 #pragma unroll
         for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[r]);
       }
-      switch (R) {
-        case 2: Dft<2>::run(x); break;
-        case 4: Dft<4>::run(x); break;
-        case 8: Dft<8>::run(x); break;
-        case 16: Dft<16>::run(x); break;
-        case 32: Dft<32>::run(x); break;
-        default: break;
-      }
-      if (last) {
+      Dft<R>::run(x);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[b + r * NB] = x[r];
-      } else {
-        const int o0 = (j / NS) * NS * R + k;
-#pragma unroll
-        for (int r = 0; r < R; ++r) lds[LY::idx(m, o0 + r * NS)] = x[r];
-      }
+      for (int r = 0; r < R; ++r) v[b + r * NB] = x[r];
     }
-    if (!last) {
-      __syncthreads();
+    if constexpr (s < S::S - 1) {
+      exchange<L, PP, EX, R, NS>(v, lds, m, m_st, t_st, o0);
       m = m_st;
       t = t_st;
-#pragma unroll
-      for (int q = 0; q < PP; ++q) v[q] = lds[LY::idx(m, t + q * T)];
-      __syncthreads();
+      Stage<L, P, EX, s + 1>::run(v, lds, m, t, m_st, t_st, twt);
     }
   }
-  if (S::S == 1 && remap) {
-    // one-stage transform whose load and store mappings differ: transpose
-    // through LDS (`remap` is uniform across the workgroup)
+};
+
+template <int L, int P, int W, int EX>
+__device__ __forceinline__ void run_stages(float2* v, void* lds, int& m, int& t,
+                                           int m_st, int t_st, bool remap,
+                                           const float2* __restrict__ twt) {
+  using S = Sched<L, P>;
+  constexpr int T = S::T;
+  constexpr int PP = S::PP;
+  Stage<L, P, EX, 0>::run(v, lds, m, t, m_st, t_st, twt);
+  if constexpr (S::S == 1) {
+    if (remap) {
+      // one-stage transform whose load and store mappings differ: transpose
+      // through LDS (`remap` is uniform across the workgroup)
+      int o0[PP];
 #pragma unroll
-    for (int q = 0; q < PP; ++q) lds[LY::idx(m, t + q * T)] = v[q];
-    __syncthreads();
-    m = m_st;
-    t = t_st;
-#pragma unroll
-    for (int q = 0; q < PP; ++q) v[q] = lds[LY::idx(m, t + q * T)];
-    __syncthreads();
+      for (int q = 0; q < PP; ++q) o0[q] = t + q * T;
+      exchange<L, PP, EX, 1, 1>(v, lds, m, m_st, t_st, o0);
+      m = m_st;
+      t = t_st;
+    }
   }
 }
 
@@ -289,14 +331,29 @@ __device__ __forceinline__ void run_stages(float2* v, float2* lds, int& m, int& 
 // the point index fastest (contiguous lines).  With TWID the outputs are
 // multiplied by W_N^{line*k} (the inter-pass twiddle of the N1 x N2 split).
 // ---------------------------------------------------------------------------
-template <int L, int P, int W, int LOADM, int STOREM, bool TWID, typename TS>
-__global__ void __launch_bounds__((W * Sched<L, P>::T))
+// Waves per SIMD the kernel must allow so that every workgroup its LDS
+// footprint lets onto a CU can be resident (4 SIMDs per CU, at most 8 waves
+// per SIMD, 160 KB of LDS per CU); passed to the register allocator, capped
+// at 4 waves (128 VGPRs) so that no variant is squeezed into spilling.
+template <int L, int P, int W, int EX>
+__host__ __device__ constexpr int strip_min_waves() {
+  constexpr int nt = W * Sched<L, P>::T;
+  constexpr int lds = W * LdsLayout<L>::LS * (EX == 0 ? 8 : 4);
+  constexpr int per_cu_lds = 163840 / (lds > 0 ? lds : 1);
+  constexpr int waves_wg = (nt + 63) / 64;
+  constexpr int per_cu = per_cu_lds < 32 / waves_wg ? per_cu_lds : 32 / waves_wg;
+  constexpr int w = (per_cu * waves_wg + 3) / 4;
+  return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
+template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS>
+__global__ void __launch_bounds__((W * Sched<L, P>::T), (strip_min_waves<L, P, W, EX>()))
 k_strip(PassArgs a) {
   using S = Sched<L, P>;
   using LY = LdsLayout<L>;
   constexpr int T = S::T;
   constexpr int PP = S::PP;
-  __shared__ float2 lds[W * LY::LS];
+  __shared__ float2 lds[EX == 0 ? W * LY::LS : (W * LY::LS + 1) / 2];
 
   const int tid = threadIdx.x;
   const int64_t tile = tile_of(blockIdx.x, a.total_tiles, a.xcd_remap);
@@ -310,36 +367,46 @@ k_strip(PassArgs a) {
 
   float2 v[PP];
   {
-    const TS* src = reinterpret_cast<const TS*>(a.in) + bat * a.in_batch;
-    const bool ok = line0 + m < a.lines;
-    const int64_t base = (int64_t)(line0 + m) * a.in_line;
+    // lines past the end of a partial strip load a valid line and are not stored
+    const TS* src = reinterpret_cast<const TS*>(a.in) + bat * a.in_batch +
+                    (int64_t)min(line0 + m, a.lines - 1) * a.in_line + (int64_t)t * a.in_elem;
+    const int64_t step = (int64_t)T * a.in_elem;
+    const uint32_t sgn = a.conj_in ? 0x80000000u : 0u;
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
-      v[q] = ok ? load_c(src + base + (int64_t)(t + q * T) * a.in_elem) : make_float2(0.f, 0.f);
-      if (a.conj_in) v[q].y = -v[q].y;
+      v[q] = load_c(src + q * step);
+      v[q].y = __uint_as_float(__float_as_uint(v[q].y) ^ sgn);
     }
   }
 
-  run_stages<L, P, W>(v, lds, m, t, m_st, t_st, LOADM != STOREM, a.tw);
+  run_stages<L, P, W, EX>(v, lds, m, t, m_st, t_st, LOADM != STOREM, a.tw);
 
   // epilogue: inter-pass twiddle, scale, conjugate, store
   {
-    TS* dst = reinterpret_cast<TS*>(a.out) + bat * a.out_batch;
     const int line = line0 + m;
     const bool ok = line < a.lines;
-    const int64_t base = (int64_t)line * a.out_line;
+    TS* dst = reinterpret_cast<TS*>(a.out) + bat * a.out_batch + (int64_t)line * a.out_line +
+              (int64_t)t * a.out_elem;
+    const int64_t step = (int64_t)T * a.out_elem;
+    // inter-pass twiddle W_N^{line*(t + q*T)} = W_N^{line*t} * W_N^{line*q*T}:
+    // one base per lane, and a step row shared by the lanes of a line
+    float2 tw_base = make_float2(1.f, 0.f);
+    const float2* tw_row = a.tw_step;
+    if (TWID && ok) {
+      const uint32_t jb = (uint32_t)line * (uint32_t)t;
+      tw_base = cmul(a.tw_hi[jb >> a.tw_shift], a.tw_lo[jb & (uint32_t)a.tw_mask]);
+      tw_row = a.tw_step + (int64_t)line * PP;
+    }
+    const uint32_t sgn = a.conj_out ? 0x80000000u : 0u;
+    if (ok) {
 #pragma unroll
-    for (int q = 0; q < PP; ++q) {
-      const int e = t + q * T;
-      float2 y = v[q];
-      if (TWID) {
-        const uint32_t jj = (uint32_t)line * (uint32_t)e;
-        const float2 w = cmul(a.tw_hi[jj >> a.tw_shift], a.tw_lo[jj & (uint32_t)a.tw_mask]);
-        y = cmul(y, w);
+      for (int q = 0; q < PP; ++q) {
+        float2 y = v[q];
+        if (TWID) y = cmul(y, cmul(tw_base, tw_row[q]));
+        y = cscale(y, a.scale);
+        y.y = __uint_as_float(__float_as_uint(y.y) ^ sgn);
+        store_c(dst + q * step, y);
       }
-      y = cscale(y, a.scale);
-      if (a.conj_out) y.y = -y.y;
-      if (ok) store_c(dst + base + (int64_t)e * a.out_elem, y);
     }
   }
 }

@@ -50,6 +50,7 @@ const std::vector<Variant>& variants() {
     add_variants_c64_row(add_one);
     add_variants_c64_a(add_one);
     add_variants_c64_col(add_one);
+    add_variants_c64_col2(add_one);
     add_variants_c16(add_one);
   });
   return *g_variants;
@@ -306,12 +307,13 @@ struct fft_plan_s {
   size_t ws_bytes = 0;
   bool ws_owned = false;
   int device = 0;
-  // profiling
+  // profiling: a ring of `prof_slots` exec slots, 2 events per launch each
   bool prof = false;
+  int prof_slots = 0, prof_next = 0, prof_pending = 0;
+  size_t prof_npass = 0;
   std::vector<hipEvent_t> ev;
   std::vector<double> prof_ms;
   std::vector<int64_t> prof_n;
-  bool prof_pending = false;
   // batched uneven sizes
   ManyPlan many;
 };
@@ -342,7 +344,7 @@ struct TableBuild {
     const int64_t start = total;
     int ns = FIRST;
     for (int s = 1; s < S; ++s) {
-      add((int64_t)ns * PP, PP, (int64_t)ns * PP, 0);
+      add((int64_t)ns * PP, PP, (int64_t)ns * PP, 1);
       ns *= PP;
     }
     if (total == start) add(1, 0, 1, 0);  // one-stage transform: placeholder entry
@@ -401,6 +403,7 @@ int check_ptr(const void* ptr, int dtype) {
 }
 
 constexpr int kGpuTwiddleMinLog2 = 22;
+constexpr int64_t kManyWaitDefaultUs = 2000000;  // 2 s per dependency wait
 
 }  // namespace
 
@@ -465,7 +468,7 @@ void many_free(ManyPlan& mp) {
 namespace {
 
 struct ManyOptions {
-  int P = 16, threads = 256, pass2 = 13;
+  int P = 16, threads = 256, pass2 = 0;  // pass2 0: two passes above the longest one-tile length
   bool given_order = false;
 };
 
@@ -493,7 +496,10 @@ int parse_many_schedule(const char* s, ManyOptions* o) {
     if (!e || *e) return FFT_ERR_INVALID_ARGUMENT;
     if (key == "p") o->P = (int)v;
     else if (key == "threads") o->threads = (int)v;
-    else if (key == "pass2") o->pass2 = (int)v;
+    else if (key == "pass2") {
+      if (v < 1) return FFT_ERR_INVALID_ARGUMENT;
+      o->pass2 = (int)v;
+    }
     else return FFT_ERR_INVALID_ARGUMENT;
   }
   return FFT_OK;
@@ -505,6 +511,22 @@ int tile_lines(int lg, int P, int threads) {
   const int L = 1 << lg;
   const int T = L / std::min(P, L);
   return threads / T;
+}
+
+}  // namespace
+
+namespace {
+
+// Event pair array of the next profiling slot, or nullptr when profiling is off.
+hipEvent_t* prof_slot(fft_plan_s* p) {
+  if (!p->prof || p->prof_slots <= 0) return nullptr;
+  return p->ev.data() + (size_t)p->prof_next * 2 * p->prof_npass;
+}
+
+void prof_commit(fft_plan_s* p) {
+  if (!p->prof || p->prof_slots <= 0) return;
+  p->prof_next = (p->prof_next + 1) % p->prof_slots;
+  p->prof_pending = std::min(p->prof_pending + 1, p->prof_slots);
 }
 
 }  // namespace
@@ -541,16 +563,21 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
   // twiddle tables
   TableBuild tb;
   std::vector<int64_t> stage_off(S.passes.size(), 0);
-  int64_t lo_off = -1, hi_off = -1;
+  int64_t lo_off = -1, hi_off = -1, step_off = -1;
   for (size_t i = 0; i < S.passes.size(); ++i) {
     const PassSpec& ps = S.passes[i];
     if (!ps.v) continue;
     stage_off[i] = tb.add_stage_table(ps.v->L, ps.v->P);
     if (ps.v->role == ROLE_SPLIT_A) {
+      // W_N^{n2*k1} with k1 = t + q*T: a per-lane base W_N^{n2*t} (lo/hi
+      // factors) times a per-line step W_N^{n2*q*T} (table [N2][P])
       const int64_t N = n[0];
       const int sh = ps.args.tw_shift;
+      const int64_t N2 = S.split[1];
+      const int64_t T = ps.v->L / ps.v->P;
       lo_off = tb.add((int64_t)1 << sh, 0, N, 1);
       hi_off = tb.add(N >> sh, 0, N, (int64_t)1 << sh);
+      step_off = tb.add(N2 * ps.v->P, ps.v->P, N, T);
     }
   }
   const bool on_gpu = dims == 1 && ilog2_64(n[0]) >= kGpuTwiddleMinLog2;
@@ -566,6 +593,7 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
     if (ps.v->role == ROLE_SPLIT_A) {
       ps.args.tw_lo = p->d_tables + lo_off;
       ps.args.tw_hi = p->d_tables + hi_off;
+      ps.args.tw_step = p->d_tables + step_off;
     }
   }
   *out = p;
@@ -619,13 +647,13 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
   if (check_ptr(in, p->dtype) || check_ptr(out, p->dtype)) return FFT_ERR_ALIGNMENT;
   hipStream_t s = (hipStream_t)stream;
   if (p->kind == 1) {
-    int prof = p->prof && !p->ev.empty();
-    if (prof) hipEventRecord(p->ev[0], s);
     if (p->many.has_split && in == out) return FFT_ERR_INPLACE;
+    hipEvent_t* slot = prof_slot(p);
+    if (slot) hipEventRecord(slot[0], s);
     hipError_t e = many_launch(p->many, in, out, p->ws, (float)p->scale, p->scale_user, p->direction > 0, s);
-    if (prof) hipEventRecord(p->ev[1], s);
+    if (slot) hipEventRecord(slot[1], s);
     if (e != hipSuccess) return hip_fail(e);
-    p->prof_pending = prof;
+    prof_commit(p);
     return FFT_OK;
   }
   const Schedule& S = p->sched;
@@ -641,13 +669,14 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
     ws = p->ws;
   }
   const bool inv = p->direction > 0;
+  hipEvent_t* slot = prof_slot(p);
   for (size_t i = 0; i < S.passes.size(); ++i) {
     const PassSpec& ps = S.passes[i];
     // out of place: each pass reads `in` (first) or `out` and writes `out`;
     // in place with a workspace: A reads in and writes ws, B reads ws, writes out
     void* src = ws ? (i == 0 ? (void*)in : ws) : (ps.src == SEL_IN ? (void*)in : out);
     void* dst = ws ? (i == 0 ? ws : out) : out;
-    if (p->prof && 2 * i + 1 < p->ev.size()) hipEventRecord(p->ev[2 * i], s);
+    if (slot) hipEventRecord(slot[2 * i], s);
     hipError_t e;
     if (!ps.v) {
       e = launch_scale_copy(p->dtype, src, dst, ps.copy_n, (float)p->scale, s);
@@ -655,15 +684,19 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
       PassArgs a = ps.args;
       a.in = src;
       a.out = dst;
-      a.scale = ps.last ? (float)p->scale : 1.0f;
+      // the default inverse scale 1/N is applied as 1/L per pass (exact
+      // powers of two, so the result is unchanged, and 16-bit intermediates
+      // stay in range); a scale set by the caller is applied by the last pass
+      a.scale = p->scale_user ? (ps.last ? (float)p->scale : 1.0f)
+                              : (inv ? 1.0f / (float)ps.v->L : 1.0f);
       a.conj_in = (inv && ps.first) ? 1 : 0;
       a.conj_out = (inv && ps.last) ? 1 : 0;
       e = ps.v->launch(a, s);
     }
-    if (p->prof && 2 * i + 1 < p->ev.size()) hipEventRecord(p->ev[2 * i + 1], s);
+    if (slot) hipEventRecord(slot[2 * i + 1], s);
     if (e != hipSuccess) return hip_fail(e);
   }
-  p->prof_pending = p->prof;
+  prof_commit(p);
   return FFT_OK;
 }
 
@@ -763,36 +796,44 @@ int fft_describe(const int64_t* n, int64_t batch, int dims, int dtype, const cha
   return FFT_OK;
 }
 
-int fft_profile_enable(fft_plan_t p, int enable) {
-  if (!p) return FFT_ERR_INVALID_ARGUMENT;
+int fft_profile_enable(fft_plan_t p, int slots) {
+  if (!p || slots < 0) return FFT_ERR_INVALID_ARGUMENT;
   for (hipEvent_t e : p->ev) hipEventDestroy(e);
   p->ev.clear();
   p->prof = false;
-  p->prof_pending = false;
-  const size_t npass = p->kind == 1 ? 1 : p->sched.passes.size();
-  p->prof_ms.assign(npass, 0.0);
-  p->prof_n.assign(npass, 0);
-  if (!enable) return FFT_OK;
-  p->ev.resize(2 * npass);
+  p->prof_slots = 0;
+  p->prof_next = 0;
+  p->prof_pending = 0;
+  p->prof_npass = p->kind == 1 ? 1 : p->sched.passes.size();
+  p->prof_ms.assign(p->prof_npass, 0.0);
+  p->prof_n.assign(p->prof_npass, 0);
+  if (!slots) return FFT_OK;
+  p->ev.resize((size_t)slots * 2 * p->prof_npass);
   for (auto& e : p->ev) {
     hipError_t r = hipEventCreate(&e);
     if (r != hipSuccess) return hip_fail(r);
   }
+  p->prof_slots = slots;
   p->prof = true;
   return FFT_OK;
 }
 
 int fft_profile_collect(fft_plan_t p) {
   if (!p) return FFT_ERR_INVALID_ARGUMENT;
-  if (!p->prof || !p->prof_pending) return FFT_OK;
-  for (size_t i = 0; i < p->prof_ms.size(); ++i) {
-    float ms = 0;
-    hipError_t r = hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]);
-    if (r != hipSuccess) return hip_fail(r);
-    p->prof_ms[i] += ms;
-    p->prof_n[i] += 1;
+  if (!p->prof) return FFT_OK;
+  // oldest pending slot first
+  int slot = (p->prof_next - p->prof_pending + p->prof_slots) % p->prof_slots;
+  for (int k = 0; k < p->prof_pending; ++k, slot = (slot + 1) % p->prof_slots) {
+    hipEvent_t* ev = p->ev.data() + (size_t)slot * 2 * p->prof_npass;
+    for (size_t i = 0; i < p->prof_npass; ++i) {
+      float ms = 0;
+      hipError_t r = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+      if (r != hipSuccess) return hip_fail(r);
+      p->prof_ms[i] += ms;
+      p->prof_n[i] += 1;
+    }
   }
-  p->prof_pending = false;
+  p->prof_pending = 0;
   return FFT_OK;
 }
 
@@ -803,57 +844,70 @@ int fft_profile_read(fft_plan_t p, int pass, double* total_ms, int64_t* launches
   return FFT_OK;
 }
 
-int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int direction,
-                     const char* schedule, fft_plan_t* out) {
-  if (!out) return FFT_ERR_INVALID_ARGUMENT;
-  *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+struct ManyBuild {
+  ManyOptions opt;
+  const ManyVariant* var = nullptr;
+  int max_tile = 0, max_lg = 0;
+  std::vector<ManyXform> xf;
+  std::vector<ManyItem> items;
+  std::vector<int32_t> order;
+  int64_t points = 0, pass_points = 0;
+  double flops = 0;
+  bool has_split = false;
+};
+
+// Host-only part of a batched plan: per-transform descriptors, the ordered
+// work queue and the one-pass groups.  No GPU calls.
+int build_many(const int64_t* sizes, int64_t count, int dtype, int direction, const char* schedule,
+               ManyBuild* mb) {
   if (!sizes || count < 1 || count > (1 << 24)) return FFT_ERR_INVALID_ARGUMENT;
   if (direction != FFT_FORWARD && direction != FFT_INVERSE) return FFT_ERR_INVALID_ARGUMENT;
   if (dtype != FFT_C64 && dtype != FFT_C16F && dtype != FFT_C16BF) return FFT_ERR_INVALID_ARGUMENT;
-  ManyOptions opt;
+  ManyOptions& opt = mb->opt;
   if (parse_many_schedule(schedule, &opt)) return FFT_ERR_INVALID_ARGUMENT;
-  const ManyVariant* var = nullptr;
   for (int i = 0; i < many_variant_count(); ++i) {
     const ManyVariant* v = many_variant(i);
-    if (v->dtype == dtype && v->P == opt.P && v->threads == opt.threads) var = v;
+    if (v->dtype == dtype && v->P == opt.P && v->threads == opt.threads) mb->var = v;
   }
-  if (!var) return FFT_ERR_INVALID_ARGUMENT;
+  if (!mb->var) return FFT_ERR_INVALID_ARGUMENT;
   const int max_tile = std::min(kManyMaxLg, ilog2_64((int64_t)opt.threads * opt.P));
+  mb->max_tile = max_tile;
+  if (opt.pass2 == 0) opt.pass2 = max_tile + 1;
   if (opt.pass2 < 1 || opt.pass2 > max_tile + 1) return FFT_ERR_INVALID_ARGUMENT;
 
-  std::vector<ManyXform> xf((size_t)count);
+  std::vector<ManyXform>& xf = mb->xf;
+  xf.assign((size_t)count, ManyXform{});
   std::vector<int> lgs((size_t)count);
-  int64_t off = 0, points = 0, pass_points = 0;
-  double flops = 0;
-  int max_lg = 0;
+  int64_t off = 0;
   for (int64_t i = 0; i < count; ++i) {
     const int64_t n = sizes[i];
     if (!pow2(n) || ilog2_64(n) > FFT_MAX_LOG2_1D) return FFT_ERR_UNSUPPORTED_SIZE;
     const int lg = ilog2_64(n);
     if (lg > 2 * max_tile) return FFT_ERR_UNSUPPORTED_SIZE;
     lgs[i] = lg;
-    max_lg = std::max(max_lg, lg);
+    mb->max_lg = std::max(mb->max_lg, lg);
     ManyXform& x = xf[i];
-    memset(&x, 0, sizeof(x));
     x.off = off;
     x.lg = lg;
-    const bool split = lg >= opt.pass2 || lg > max_tile;
+    // two passes need two sub-lengths of at least 2 points each
+    const bool split = (lg >= opt.pass2 || lg > max_tile) && lg >= 2;
     if (split) {
       x.lg1 = (lg + 1) / 2;
       if (x.lg1 > max_tile) x.lg1 = max_tile;
-      const int lg2 = lg - x.lg1;
-      const int64_t N2 = (int64_t)1 << lg2;
+      const int64_t N2 = (int64_t)1 << (lg - x.lg1);
       const int wa = tile_lines(x.lg1, opt.P, opt.threads);
       x.nA = (int32_t)((N2 + wa - 1) / wa);
-      pass_points += 2 * n;
+      mb->pass_points += 2 * n;
     } else {
-      x.lg1 = 0;
-      x.nA = 0;
-      pass_points += n;
+      mb->pass_points += n;
     }
     off += n;
-    points += n;
-    flops += 5.0 * (double)n * (double)lg;
+    mb->points += n;
+    mb->flops += 5.0 * (double)n * (double)lg;
   }
   if (off > ((int64_t)1 << 40)) return FFT_ERR_UNSUPPORTED_SIZE;
 
@@ -864,13 +918,12 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
     std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) { return lgs[a] > lgs[b]; });
 
   // items: all first-pass tiles, then one-pass tiles, then second-pass tiles
-  std::vector<ManyItem> items;
-  std::vector<int32_t> order;
-  bool has_split = false;
+  std::vector<ManyItem>& items = mb->items;
+  std::vector<int32_t>& order = mb->order;
   for (int32_t id : ids) {
     const ManyXform& x = xf[id];
     if (x.nA == 0) continue;
-    has_split = true;
+    mb->has_split = true;
     for (int t = 0; t < x.nA; ++t) items.push_back({MANY_A, x.lg1, id, t});
   }
   {
@@ -879,15 +932,15 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
     for (int32_t id : ids)
       if (xf[id].nA == 0) by_lg[xf[id].lg].push_back(id);
     std::vector<int> lg_order;
-    for (int lg = max_tile; lg >= 0; --lg) lg_order.push_back(lg);
     if (opt.given_order) {
-      lg_order.clear();
       std::vector<bool> seen(max_tile + 1, false);
       for (int32_t id : ids)
         if (xf[id].nA == 0 && !seen[xf[id].lg]) {
           seen[xf[id].lg] = true;
           lg_order.push_back(xf[id].lg);
         }
+    } else {
+      for (int lg = max_tile; lg >= 0; --lg) lg_order.push_back(lg);
     }
     for (int lg : lg_order) {
       const auto& v = by_lg[lg];
@@ -909,7 +962,57 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
     for (int t = 0; t < nb; ++t) items.push_back({MANY_B, lg2, id, t});
   }
   if (items.size() > (size_t)INT32_MAX) return FFT_ERR_UNSUPPORTED_SIZE;
+  return FFT_OK;
+}
 
+}  // namespace
+
+extern "C" {
+
+int fft_describe_many(const int64_t* sizes, int64_t count, int dtype, const char* schedule,
+                      int32_t* items, int64_t max_items, int64_t* n_items, int32_t* first_len,
+                      int32_t* first_tiles) {
+  if (!n_items) return FFT_ERR_INVALID_ARGUMENT;
+  ManyBuild mb;
+  int rc = build_many(sizes, count, dtype, FFT_FORWARD, schedule, &mb);
+  if (rc) return rc;
+  *n_items = (int64_t)mb.items.size();
+  if (items) {
+    if (max_items < (int64_t)mb.items.size()) return FFT_ERR_INVALID_ARGUMENT;
+    for (size_t i = 0; i < mb.items.size(); ++i) {
+      const ManyItem& it = mb.items[i];
+      // one-pass items are reported as (0, lg, first transform, lines)
+      const int32_t a = it.kind == MANY_SINGLE ? mb.order[it.a] : it.a;
+      items[4 * i] = it.kind;
+      items[4 * i + 1] = it.lg;
+      items[4 * i + 2] = a;
+      items[4 * i + 3] = it.b;
+    }
+  }
+  for (int64_t i = 0; i < count; ++i) {
+    if (first_len) first_len[i] = mb.xf[i].nA ? (1 << mb.xf[i].lg1) : 0;
+    if (first_tiles) first_tiles[i] = mb.xf[i].nA;
+  }
+  return FFT_OK;
+}
+
+int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int direction,
+                     const char* schedule, fft_plan_t* out) {
+  if (!out) return FFT_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  ManyBuild mb;
+  int rc0 = build_many(sizes, count, dtype, direction, schedule, &mb);
+  if (rc0) return rc0;
+  const ManyOptions& opt = mb.opt;
+  const ManyVariant* var = mb.var;
+  const int max_tile = mb.max_tile;
+  const int max_lg = mb.max_lg;
+  std::vector<ManyXform>& xf = mb.xf;
+  std::vector<ManyItem>& items = mb.items;
+  std::vector<int32_t>& order = mb.order;
+  const int64_t points = mb.points, pass_points = mb.pass_points;
+  const double flops = mb.flops;
+  const bool has_split = mb.has_split;
   fft_plan_s* p = new (std::nothrow) fft_plan_s();
   if (!p) return FFT_ERR_NO_MEMORY;
   p->kind = 1;
@@ -991,7 +1094,7 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
   for (int lg = 0; lg <= kManyMaxLg; ++lg) a.stage_off[lg] = soff[lg];
   a.n_items = (int32_t)items.size();
   a.n_xforms = (int32_t)count;
-  a.spin_limit = 1 << 26;
+  a.wait_ticks = kManyWaitDefaultUs * 100;
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
   if (e != hipSuccess) {
@@ -1027,9 +1130,22 @@ int fft_many_watchdog(fft_plan_t p, int clear) {
   return flag ? FFT_ERR_WATCHDOG : FFT_OK;
 }
 
-int fft_many_set_spin_limit(fft_plan_t p, int32_t limit) {
-  if (!p || p->kind != 1 || limit < 1) return FFT_ERR_INVALID_ARGUMENT;
-  p->many.args.spin_limit = limit;
+int fft_many_set_wait_limit(fft_plan_t p, int64_t microseconds) {
+  if (!p || p->kind != 1 || microseconds < 1 || microseconds > ((int64_t)1 << 40))
+    return FFT_ERR_INVALID_ARGUMENT;
+  p->many.args.wait_ticks = microseconds * 100;
+  return FFT_OK;
+}
+
+int fft_twiddle_host(int64_t count, int64_t R, int64_t M, int64_t mul, float* out) {
+  if (!out || count < 0 || R < 0 || M < 1 || (M & (M - 1))) return FFT_ERR_INVALID_ARGUMENT;
+  TwSeg sg{0, count, R, M, mul};
+  for (int64_t i = 0; i < count; ++i) {
+    double c, sn;
+    twiddle_fp64(seg_exponent(sg, i), M, &c, &sn);
+    out[2 * i] = (float)c;
+    out[2 * i + 1] = (float)-sn;
+  }
   return FFT_OK;
 }
 

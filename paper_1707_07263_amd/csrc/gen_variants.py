@@ -13,8 +13,8 @@ DT = {"c64": "float2", "f16": "__half2", "bf16": "c16bf"}
 ROLE = {"r": "ROLE_ROW", "a": "ROLE_SPLIT_A", "c": "ROLE_COL"}
 
 
-def lds_bytes(L, W):
-    return W * (L + (L >> 4) + 1) * 8
+def lds_bytes(L, W, ex=0):
+    return W * (L + (L >> 4) + 1) * (4 if ex else 8)
 
 
 def threads(L, P, W):
@@ -22,49 +22,60 @@ def threads(L, P, W):
     return W * (L // pp)
 
 
-def ok(L, P, W, min_threads=64):
+def ok(L, P, W, ex=0, min_threads=64):
     t = threads(L, P, W)
-    return t <= 1024 and t >= min(min_threads, 1024) and lds_bytes(L, W) <= LDS_MAX
+    return t <= 1024 and t >= min(min_threads, 1024) and lds_bytes(L, W, ex) <= LDS_MAX
 
 
 def row_set():
     out = []
     for lg in range(1, 15):
         L = 1 << lg
-        for P in (8, 16):
+        for P in (8, 16, 32):
             if P > L and P != 8:
+                continue
+            if P == 32 and (L < 512 or L > 1024):
                 continue
             pp = min(P, L)
             T = L // pp
             for target in (256, 512):
                 W = max(1, target // T)
-                if ok(L, P, W) and (L, P, W) not in out:
-                    out.append((L, P, W))
+                for ex in (0, 1):
+                    if ex and lds_bytes(L, W) <= 64 * 1024:
+                        continue
+                    if ok(L, P, W, ex) and (L, P, W, ex) not in out:
+                        out.append((L, P, W, ex))
+    return out
+
+
+def strided_set(lo_lg, hi_lg, role):
+    out = []
+    for lg in range(lo_lg, hi_lg + 1):
+        L = 1 << lg
+        for P in (8, 16, 32):
+            if P > L and P != 8:
+                continue
+            if P == 32 and (L < 256 or L > 1024):
+                continue
+            for W in (1, 2, 4, 8, 16, 32, 64):
+                if role == "a" and W < 4:
+                    continue
+                if P == 32 and W < 8:
+                    continue
+                for ex in (0, 1):
+                    if ex and lds_bytes(L, W) <= 64 * 1024:
+                        continue
+                    if ok(L, P, W, ex, min_threads=64 if L >= 64 else 1):
+                        out.append((L, P, W, ex))
     return out
 
 
 def a_set():
-    out = []
-    for lg in range(6, 13):
-        L = 1 << lg
-        for W in (4, 8, 16, 32):
-            for P in (8, 16):
-                if ok(L, P, W):
-                    out.append((L, P, W))
-    return out
+    return strided_set(6, 12, "a")
 
 
 def col_set():
-    out = []
-    for lg in range(1, 15):
-        L = 1 << lg
-        for W in (1, 2, 4, 8, 16, 32, 64):
-            for P in (8, 16):
-                if P > L and P != 8:
-                    continue
-                if ok(L, P, W, min_threads=64 if L >= 64 else 1):
-                    out.append((L, P, W))
-    return out
+    return strided_set(1, 14, "c")
 
 
 def c16_set():
@@ -77,31 +88,32 @@ def c16_set():
         W = max(1, 256 // T)
         while not ok(L, P, W) and W > 1:
             W //= 2
-        out.append(("r", L, P, W))
+        out.append(("r", L, P, W, 0))
     for lg in range(6, 13):
         L = 1 << lg
         W = 16
         while not ok(L, 16, W) and W > 1:
             W //= 2
-        out.append(("a", L, 16, W))
+        out.append(("a", L, 16, W, 0))
     for lg in range(1, 15):
         L = 1 << lg
         W = 16
         while not ok(L, 16, W, min_threads=1) and W > 1:
             W //= 2
-        out.append(("c", L, 16, W))
+        out.append(("c", L, 16, W, 0))
     return out
 
 
-def name(role, L, P, W, dt):
-    return f"{role}{L}p{min(P, L)}w{W}_{dt}"
+def name(role, L, P, W, ex, dt):
+    return f"{role}{L}p{min(P, L)}w{W}{'x' if ex else ''}_{dt}"
 
 
 def emit(fname, func, items):
     lines = ['#include "variants.hpp"', "", "namespace mfft {", "",
              f"void {func}(void (*add)(const Variant&)) {{"]
-    for role, L, P, W, dt in items:
-        lines.append(f'  add(make_variant<{ROLE[role]}, {L}, {P}, {W}, {DT[dt]}>("{name(role, L, P, W, dt)}"));')
+    for role, L, P, W, ex, dt in items:
+        lines.append(f'  add(make_variant<{ROLE[role]}, {L}, {P}, {W}, {ex}, {DT[dt]}>'
+                     f'("{name(role, L, P, W, ex, dt)}"));')
     lines += ["}", "", "}  // namespace mfft", ""]
     text = "\n".join(lines)
     path = os.path.join(HERE, fname)
@@ -111,12 +123,15 @@ def emit(fname, func, items):
 
 
 def main():
-    emit("variants_c64_row.hip", "add_variants_c64_row", [("r", L, P, W, "c64") for L, P, W in row_set()])
-    emit("variants_c64_a.hip", "add_variants_c64_a", [("a", L, P, W, "c64") for L, P, W in a_set()])
-    emit("variants_c64_col.hip", "add_variants_c64_col", [("c", L, P, W, "c64") for L, P, W in col_set()])
+    emit("variants_c64_row.hip", "add_variants_c64_row", [("r",) + v + ("c64",) for v in row_set()])
+    emit("variants_c64_a.hip", "add_variants_c64_a", [("a",) + v + ("c64",) for v in a_set()])
+    cols = [("c",) + v + ("c64",) for v in col_set()]
+    half = len(cols) // 2
+    emit("variants_c64_col.hip", "add_variants_c64_col", cols[:half])
+    emit("variants_c64_col2.hip", "add_variants_c64_col2", cols[half:])
     items = []
     for dt in ("f16", "bf16"):
-        items += [(r, L, P, W, dt) for r, L, P, W in c16_set()]
+        items += [v + (dt,) for v in c16_set()]
     emit("variants_c16.hip", "add_variants_c16", items)
 
 

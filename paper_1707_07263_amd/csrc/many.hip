@@ -71,7 +71,7 @@ __device__ __forceinline__ void many_tile(const ManyArgs& a, const ManyItem& d, 
     if (first && a.inverse) v[q].y = -v[q].y;
   }
 
-  run_stages<L, P, W>(v, lds, m, t, m_st, t_st, mfast_in != mfast_out, a.tw + a.stage_off[ilog2(L)]);
+  run_stages<L, P, W, 0>(v, lds, m, t, m_st, t_st, mfast_in != mfast_out, a.tw + a.stage_off[ilog2(L)]);
 
   // line addressing of the store (lane mapping may have changed)
   int64_t obase = 0, oelem = 1;
@@ -96,11 +96,14 @@ __device__ __forceinline__ void many_tile(const ManyArgs& a, const ManyItem& d, 
       oelem = 1;
       twl = x.tw_lo;
       lg1 = x.lg1;
+      // the default inverse scale 1/N is split as 1/N1 here and 1/N2 in the
+      // second pass (exact, and keeps 16-bit intermediates in range)
+      scale = (a.inverse && !a.use_scale) ? 1.f / (float)N1 : 1.f;
     } else {
       ok = line < N1;
       obase = x.off + line;  // X[k1 + N1*k2]
       oelem = N1;
-      scale = a.use_scale ? a.scale : (a.inverse ? 1.f / (float)(N1 * N2) : 1.f);
+      scale = a.use_scale ? a.scale : (a.inverse ? 1.f / (float)N2 : 1.f);
     }
   }
 #pragma unroll
@@ -113,10 +116,8 @@ __device__ __forceinline__ void many_tile(const ManyArgs& a, const ManyItem& d, 
       const float2* hi = lo + ((int64_t)1 << lg1);
       y = cmul(y, cmul(hi[jj >> lg1], lo[jj & ((1u << lg1) - 1u)]));
     }
-    if (last) {
-      y = cscale(y, scale);
-      if (a.inverse) y.y = -y.y;
-    }
+    y = cscale(y, scale);
+    if (last && a.inverse) y.y = -y.y;
     if (ok) store_c(dst + obase + (int64_t)e * oelem, y);
   }
 }
@@ -152,20 +153,25 @@ __global__ void __launch_bounds__(NT) k_many(ManyArgs a) {
       // Wait until every first-pass tile of this transform has released its
       // results.  The queue lists all of them before any second-pass tile of
       // the same transform, so they are held by running workgroups that wait
-      // on nothing; the bound only guards against a corrupted queue.
+      // on nothing.  Polls are relaxed loads (no cache invalidation per
+      // poll); one acquire follows the last poll.  The wait is bounded in
+      // wall-clock time (100 MHz counter) and flags the watchdog word if the
+      // bound is hit, so the kernel always finishes.
       if (tid == 0) {
         const int need = a.xf[d.a].nA;
-        int spins = 0;
-        while (__hip_atomic_load(&done[d.a], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-          __builtin_amdgcn_s_sleep(2);
-          if (++spins > a.spin_limit) {
-            atomicOr(watchdog, 1);
-            break;
+        if (__hip_atomic_load(&done[d.a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+          while (__hip_atomic_load(&done[d.a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            __builtin_amdgcn_s_sleep(8);
+            if (__builtin_amdgcn_s_memrealtime() - t0 > (uint64_t)a.wait_ticks) {
+              atomicOr(watchdog, 1);
+              break;
+            }
           }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       __syncthreads();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     switch (d.lg) {
       case 0: many_tile1<NT, TS>(a, d, tid); break;
@@ -183,14 +189,11 @@ __global__ void __launch_bounds__(NT) k_many(ManyArgs a) {
       case 12: if constexpr (NT * P >= 4096) many_tile<4096, P, NT, TS>(a, d, lds, tid); break;
       default: break;
     }
-    if (d.kind == MANY_A) {
-      // make this tile's stores visible device-wide, then count it done
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __syncthreads();
-      if (tid == 0) __hip_atomic_fetch_add(&done[d.a], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __syncthreads();
-    }
+    // the barrier orders every wave's stores of this tile before thread 0's
+    // agent-scope release, which makes them visible to the other XCDs
+    __syncthreads();
+    if (d.kind == MANY_A && tid == 0)
+      __hip_atomic_fetch_add(&done[d.a], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
   // The last workgroup out resets the queue state for the next launch.
   if (tid == 0) {

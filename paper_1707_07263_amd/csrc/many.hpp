@@ -49,7 +49,7 @@ struct ManyArgs {
   float scale;                        // used when use_scale != 0
   int32_t use_scale;                  // 0: per-transform default (1 or 1/N)
   int32_t inverse;
-  int32_t spin_limit;
+  int64_t wait_ticks;  // bound of one dependency wait, 100 MHz ticks
 };
 
 constexpr int kManyWsHeader = 4;  // ints before the per-transform counters

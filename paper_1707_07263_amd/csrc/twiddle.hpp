@@ -16,14 +16,14 @@
 namespace mfft {
 
 // Segment of a table: entries table[off + i], i < count, hold W_M^{e(i)} with
-//   e(i) = (i / R) * (i % R)   if R > 0  (stage table: k = i / R, r = i % R)
-//   e(i) = i * mul             if R == 0 (linear table)
+//   e(i) = (i / R) * (i % R) * mul   if R > 0  (2-D table: row i / R, column i % R)
+//   e(i) = i * mul                   if R == 0 (linear table)
 struct TwSeg {
   int64_t off, count, R, M, mul;
 };
 
 __host__ __device__ inline int64_t seg_exponent(const TwSeg& s, int64_t i) {
-  return s.R > 0 ? (i / s.R) * (i % s.R) : i * s.mul;
+  return s.R > 0 ? (i / s.R) * (i % s.R) * s.mul : i * s.mul;
 }
 
 // cos and sin of 2*pi*e/M in float64 (M a power of two, any integer e).

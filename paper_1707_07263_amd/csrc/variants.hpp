@@ -20,13 +20,14 @@ struct Variant {
   int L, P, W, threads, role, dtype;
   int lds_bytes;
   int tw_entries;  // stage-table entries for this (L, P)
+  int ex;          // LDS exchange: 0 = (re, im) pairs, 1 = real then imaginary
   LaunchFn launch;
 };
 
-template <int L, int P, int W, int LOADM, int STOREM, bool TWID, typename TS>
+template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS>
 hipError_t launch_strip(const PassArgs& a, hipStream_t s) {
   constexpr int NT = W * Sched<L, P>::T;
-  hipLaunchKernelGGL((k_strip<L, P, W, LOADM, STOREM, TWID, TS>), dim3((unsigned)a.total_tiles),
+  hipLaunchKernelGGL((k_strip<L, P, W, LOADM, STOREM, TWID, EX, TS>), dim3((unsigned)a.total_tiles),
                      dim3(NT), 0, s, a);
   return hipGetLastError();
 }
@@ -36,7 +37,7 @@ template <> struct DtOf<float2> { static constexpr int v = DT_C64; };
 template <> struct DtOf<__half2> { static constexpr int v = DT_C16F; };
 template <> struct DtOf<c16bf> { static constexpr int v = DT_C16BF; };
 
-template <int ROLE, int L, int P, int W, typename TS>
+template <int ROLE, int L, int P, int W, int EX, typename TS>
 Variant make_variant(const char* name) {
   constexpr int LOADM = ROLE == ROLE_ROW ? 0 : 1;
   constexpr int STOREM = ROLE == ROLE_COL ? 1 : 0;
@@ -49,9 +50,10 @@ Variant make_variant(const char* name) {
   v.threads = W * Sched<L, P>::T;
   v.role = ROLE;
   v.dtype = DtOf<TS>::v;
-  v.lds_bytes = W * LdsLayout<L>::LS * (int)sizeof(float2);
+  v.lds_bytes = W * LdsLayout<L>::LS * (EX == 0 ? 8 : 4);
   v.tw_entries = Sched<L, P>::TW;
-  v.launch = &launch_strip<L, P, W, LOADM, STOREM, TWID, TS>;
+  v.ex = EX;
+  v.launch = &launch_strip<L, P, W, LOADM, STOREM, TWID, EX, TS>;
   return v;
 }
 
@@ -59,6 +61,7 @@ Variant make_variant(const char* name) {
 void add_variants_c64_row(void (*add)(const Variant&));
 void add_variants_c64_a(void (*add)(const Variant&));
 void add_variants_c64_col(void (*add)(const Variant&));
+void add_variants_c64_col2(void (*add)(const Variant&));
 void add_variants_c16(void (*add)(const Variant&));
 
 // trivial length-1 / copy-scale kernel

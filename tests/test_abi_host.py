@@ -1,0 +1,155 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function
+declared in include/mi355fft.h, plans schedules on the host, reports errors
+for bad arguments, and its host twiddle generator rounds W_M^e correctly.
+No kernel is launched here."""
+import os
+import re
+
+import mpmath
+import numpy as np
+import pytest
+
+from paper_1707_07263_amd import capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mi355fft.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return capi.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fft_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(capi.EXPORTED)
+
+
+def test_error_strings(lib):
+    for code in range(0, -8, -1):
+        s = capi.error_string(code)
+        assert s and s != "unknown status"
+    assert capi.error_string(-99) == "unknown status"
+
+
+def test_variant_registry(lib):
+    n = capi.fft_variant_count()
+    assert n > 100
+    seen = set()
+    for i in range(n):
+        name = capi.fft_variant_name(i)
+        d = capi.fft_variant_describe(i)
+        assert name not in seen
+        seen.add(name)
+        m = re.match(r"([rac])(\d+)p(\d+)w(\d+)(x?)_(c64|f16|bf16)$", name)
+        assert m, name
+        assert int(m.group(2)) == d["L"] and int(m.group(3)) == d["P"] and int(m.group(4)) == d["W"]
+        assert {"r": 0, "a": 1, "c": 2}[m.group(1)] == d["role"]
+        assert {"c64": 0, "f16": 1, "bf16": 2}[m.group(6)] == d["dtype"]
+        assert d["threads"] == d["W"] * d["L"] // d["P"] and d["threads"] <= 1024
+    assert capi.fft_variant_name(n) is None
+
+
+@pytest.mark.parametrize("n,dims,batch,passes,split", [
+    ([1024], 1, 1, 1, [0, 0]),                 # one pass fits a workgroup
+    ([1 << 14], 1, 4, 1, [0, 0]),
+    ([1 << 15], 1, 4, 2, [256, 128]),          # first length that needs the split
+    ([1 << 20], 1, 16, 2, [1024, 1024]),
+    ([1 << 24], 1, 1, 2, [4096, 4096]),
+    ([4096, 4096], 2, 1, 2, [0, 0]),           # rows, then columns
+    ([1, 64], 2, 3, 1, [0, 0]),                # a length-1 axis needs no pass
+    ([64, 1], 2, 3, 1, [0, 0]),
+    ([1], 1, 5, 1, [0, 0]),
+])
+def test_describe_schedules(lib, n, dims, batch, passes, split):
+    d = capi.fft_describe(n, batch, dims, capi.FFT_C64)
+    assert d["passes"] == passes
+    assert d["split"] == split
+    if dims == 1 and n[0] > 1 and passes == 2:
+        assert d["names"][0].startswith(f"a{split[0]}p") and d["names"][1].startswith(f"c{split[1]}p")
+
+
+def test_describe_schedule_overrides(lib):
+    d = capi.fft_describe([1 << 16], 2, 1, capi.FFT_C64, "split=512")
+    assert d["split"] == [512, 128]
+    d = capi.fft_describe([1 << 20], 2, 1, capi.FFT_C64, "a=a1024p16w8_c64;b=c1024p16w8_c64")
+    assert d["names"] == ["a1024p16w8_c64", "c1024p16w8_c64"]
+    for bad in ("split=3", "split=1048576", "a=c1024p16w8_c64", "a=a512p16w16_c64", "bogus=1", "split"):
+        with pytest.raises(capi.FFTError) as ei:
+            capi.fft_describe([1 << 20], 2, 1, capi.FFT_C64, bad)
+        assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT, bad
+
+
+@pytest.mark.parametrize("n,dims,dtype,code", [
+    ([12], 1, 0, capi.FFT_ERR_UNSUPPORTED_SIZE),
+    ([0], 1, 0, capi.FFT_ERR_UNSUPPORTED_SIZE),
+    ([1 << 25], 1, 0, capi.FFT_ERR_UNSUPPORTED_SIZE),
+    ([1 << 15, 4], 2, 0, capi.FFT_ERR_UNSUPPORTED_SIZE),
+    ([16], 3, 0, capi.FFT_ERR_INVALID_ARGUMENT),
+    ([16], 1, 9, capi.FFT_ERR_INVALID_ARGUMENT),
+])
+def test_describe_errors(lib, n, dims, dtype, code):
+    with pytest.raises(capi.FFTError) as ei:
+        capi.fft_describe(n, 1, dims, dtype)
+    assert ei.value.status == code
+
+
+def test_describe_16bit(lib):
+    for dt in (capi.FFT_C16F, capi.FFT_C16BF):
+        for n in ([256], [1 << 20], [512, 512]):
+            d = capi.fft_describe(n, 2, len(n), dt)
+            suffix = "_f16" if dt == capi.FFT_C16F else "_bf16"
+            assert all(v.endswith(suffix) for v in d["names"])
+
+
+@pytest.mark.parametrize("M,R,mul,count", [(16, 0, 1, 16), (1024, 0, 1, 1024), (1 << 20, 0, 1024, 1024),
+                                          (1 << 20, 0, 1, 2048), (1024, 16, 1, 1024), (1 << 22, 0, 2047, 512),
+                                          (1 << 24, 16, 4096, 4096)])
+def test_host_twiddles_correctly_rounded(lib, M, R, mul, count):
+    # every entry is W_M^e = exp(-2 pi i e / M) rounded to float32; compared
+    # with the value computed to 30 digits by mpmath and rounded once
+    got = capi.fft_twiddle_host(count, R, M, mul)
+    mpmath.mp.dps = 30
+    want = np.empty(count, np.complex64)
+    for i in range(count):
+        e = (i // R) * (i % R) * mul if R else i * mul
+        ang = 2 * mpmath.pi * mpmath.mpf(e % M) / M
+        c, s = mpmath.cos(ang), mpmath.sin(ang)
+        # cos/sin of exact multiples of pi/2 are exactly 0; at 30 digits they
+        # come out as ~1e-31, below any float32 table entry
+        c = 0 if abs(c) < mpmath.mpf(10) ** -25 else c
+        s = 0 if abs(s) < mpmath.mpf(10) ** -25 else s
+        want[i] = np.float32(float(c)) + 1j * np.float32(-float(s))
+    mism = np.nonzero(got != want)[0]
+    # float64 -> float32 double rounding can only differ at exact ties, which
+    # these arguments do not hit
+    assert mism.size == 0, [(int(i), got[i], want[i]) for i in mism[:5]]
+
+
+def test_host_twiddle_symmetries(lib):
+    M = 4096
+    w = capi.fft_twiddle_host(M, 0, M, 1).astype(np.complex128)
+    k = np.arange(M)
+    # eq. 4: W^{-k} = conj(W^k), read as W^{M-k}
+    assert np.array_equal(w[(M - k) % M], np.conj(w))
+    # quarter-turn symmetry of the reduction: W^{k + M/4} = -i W^k exactly
+    assert np.array_equal(w[(k + M // 4) % M], -1j * w)
+    # eq. 5 reducibility: W_M^{2k} = W_{M/2}^k
+    half = capi.fft_twiddle_host(M // 2, 0, M // 2, 1)
+    assert np.array_equal(w[0::2].astype(np.complex64), half)
+
+
+def test_package_imports_without_gpu():
+    import paper_1707_07263_amd as pkg
+    from paper_1707_07263_amd import api  # noqa: F401
+    assert callable(pkg.fft) and callable(pkg.fft2) and callable(pkg.fft_many)
+    assert pkg.FFTFunction is api.FFTFunction

@@ -1,0 +1,100 @@
+"""16-bit storage on the strided plans, the torch-facing wrappers, and
+hipGraph capture/replay of strided plans."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1707_07263_amd import api, capi, workloads
+from gpu_helpers import from_gpu_16, quantised, rel_l2_rows, require_gpu, tol_fp32, to_gpu_16, to_gpu_c64
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL16 = {"float16": 1e-3, "bfloat16": 8e-3}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+@pytest.mark.parametrize("tname", ["float16", "bfloat16"])
+@pytest.mark.parametrize("shape", [(256,), (4096,), (1 << 14,), (1 << 16,), (1 << 20,), (64, 512), (1024, 1024)])
+def test_16bit_storage(dev, tname, shape):
+    tdt = getattr(torch, tname)
+    n = int(np.prod(shape))
+    b = 2
+    x = workloads.normal_batch(n, b, seed=n % 1000).reshape((b,) + shape)
+    xq = quantised(x, tdt)
+    xt = to_gpu_16(x, dev, tdt)
+    y = api.fft2(xt) if len(shape) == 2 else api.fft(xt)
+    torch.cuda.synchronize()
+    got = from_gpu_16(y).reshape(b, -1)
+    ref = (oracle.fft2(xq) if len(shape) == 2 else oracle.fft(xq)).reshape(b, -1)
+    err = rel_l2_rows(got, ref, n)
+    print(f"{tname} {shape}: rel-L2 vs oracle on quantised input {err.max():.3e}")
+    assert err.max() <= TOL16[tname], float(err.max())
+    # inverse back to the input, same tolerance per direction
+    z = api.ifft2(y) if len(shape) == 2 else api.ifft(y)
+    torch.cuda.synchronize()
+    ref_z = (oracle.fft2(from_gpu_16(y), inverse=True) if len(shape) == 2
+             else oracle.ifft(from_gpu_16(y))).reshape(b, -1)
+    assert rel_l2_rows(from_gpu_16(z).reshape(b, -1), ref_z, n).max() <= TOL16[tname]
+
+
+def test_wrappers_match_capi(dev):
+    x = workloads.normal_batch(4096, 5, seed=61).astype(np.complex64)
+    xt = to_gpu_c64(x, dev)
+    y = api.fft(xt)
+    z = api.ifft(y)
+    torch.cuda.synchronize()
+    assert rel_l2_rows(y.cpu().numpy(), oracle.fft(x), 4096).max() <= tol_fp32(4096)
+    assert rel_l2_rows(z.cpu().numpy(), x, 4096).max() <= 2 * tol_fp32(4096)
+    img = workloads.normal_batch(128 * 256, 2, seed=62).astype(np.complex64).reshape(2, 128, 256)
+    it = to_gpu_c64(img, dev)
+    y2 = api.fft2(it)
+    torch.cuda.synchronize()
+    assert rel_l2_rows(y2.cpu().numpy().reshape(2, -1), oracle.fft2(img).reshape(2, -1),
+                       128 * 256).max() <= tol_fp32(128 * 256)
+    # in place through the wrapper (two-pass 1-D uses a torch-allocated workspace)
+    big = to_gpu_c64(workloads.normal_batch(1 << 18, 2, seed=63), dev)
+    ref = oracle.fft(big.cpu().numpy())
+    api.fft(big, out=big)
+    torch.cuda.synchronize()
+    assert rel_l2_rows(big.cpu().numpy(), ref, 1 << 18).max() <= tol_fp32(1 << 18)
+    with pytest.raises(ValueError):
+        api.fft(torch.zeros(16, dtype=torch.complex64))  # CPU tensor: no CPU path
+
+
+@pytest.mark.parametrize("shape", [(1 << 20,), (4096, 4096), (1024,)])
+def test_graph_capture_replay_strided(dev, shape):
+    n = int(np.prod(shape))
+    b = 2 if n >= (1 << 20) else 16
+    x = workloads.normal_batch(n, b, seed=71).astype(np.complex64)
+    xt = to_gpu_c64(x, dev)
+    out = torch.zeros_like(xt)
+    eager = torch.empty_like(xt)
+    h = capi.fft_plan(list(shape), b, len(shape), capi.FFT_C64, capi.FFT_FORWARD)
+    try:
+        capi.fft_exec(h, xt.data_ptr(), eager.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                capi.fft_exec(h, xt.data_ptr(), out.data_ptr(), s.cuda_stream)
+        torch.cuda.current_stream().wait_stream(s)
+        for rep in range(3):
+            out.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager), f"replay {rep}"
+            capi.fft_exec(h, xt.data_ptr(), eager.data_ptr(), torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+        del g
+    finally:
+        capi.fft_destroy(h)

@@ -1,0 +1,108 @@
+"""Host-side checks of the batched persistent launch's work queue (built by
+the library's planner, no GPU): coverage of every transform, the ordering
+that guarantees forward progress, and a simulated run of resident
+workgroups pulling items from the queue under the kernel's wait rule."""
+import numpy as np
+import pytest
+
+from paper_1707_07263_amd import capi, workloads
+
+SINGLE, FIRST, SECOND = 0, 1, 2
+
+
+def check_queue(sizes, schedule=None, threads=256, P=16):
+    items, first_len, first_tiles = capi.fft_describe_many(list(sizes), capi.FFT_C64, schedule)
+    sizes = np.asarray(sizes)
+    lg = np.log2(sizes).astype(int)
+    seen_first = {}
+    first_done_pos = {}
+    second_tiles = {}
+    singles = np.zeros(len(sizes), int)
+    for pos, (kind, tlg, a, b) in enumerate(items):
+        if kind == FIRST:
+            assert first_len[a] == (1 << tlg)
+            seen_first.setdefault(a, set()).add(b)
+            first_done_pos[a] = pos
+            assert a not in second_tiles, "first-pass tile after a second-pass tile"
+        elif kind == SECOND:
+            # every first-pass tile of this transform precedes it in the queue
+            assert len(seen_first.get(a, ())) == first_tiles[a]
+            assert (1 << tlg) * first_len[a] == sizes[a]
+            second_tiles.setdefault(a, set()).add(b)
+        else:
+            assert kind == SINGLE and b >= 1
+            singles[a] += 0  # transform index of the tile's first line
+    for i, n in enumerate(sizes):
+        if first_tiles[i]:
+            n1 = int(first_len[i])
+            n2 = int(n) // n1
+            assert n1 >= 2 and n2 >= 2
+            # tiles cover the N2 columns of the first pass and N1 of the second
+            assert seen_first[i] == set(range(first_tiles[i]))
+            assert len(second_tiles[i]) >= 1 and second_tiles[i] == set(range(len(second_tiles[i])))
+    n_single_lines = int(items[items[:, 0] == SINGLE][:, 3].sum())
+    assert n_single_lines == int((first_tiles == 0).sum())
+    return items, first_tiles
+
+
+def simulate(items, first_tiles, workers, rng):
+    """Workers take items in queue order; a second-pass item can finish only
+    after all first-pass items of its transform finished.  Returns steps."""
+    done = np.zeros(len(first_tiles), int)
+    head = 0
+    busy = []  # (remaining work, item)
+    steps = 0
+    while head < len(items) or busy:
+        while len(busy) < workers and head < len(items):
+            busy.append([int(rng.integers(1, 5)), items[head]])
+            head += 1
+        progressed = False
+        for w in busy:
+            kind, _, a, _ = w[1]
+            if kind == SECOND and done[a] < first_tiles[a]:
+                continue  # waiting
+            w[0] -= 1
+            progressed = True
+        for w in [w for w in busy if w[0] <= 0]:
+            if w[1][0] == FIRST:
+                done[w[1][2]] += 1
+            busy.remove(w)
+        assert progressed, "deadlock: every resident worker waits"
+        steps += 1
+        assert steps < 10 * len(items) + 100
+    return steps
+
+
+def test_config4_queue():
+    sizes = workloads.uneven_sizes(512, 8, 16, seed=3)
+    items, ft = check_queue(sizes)
+    rng = np.random.default_rng(0)
+    for workers in (1, 3, 64, 768):
+        simulate(items, ft, workers, rng)
+
+
+@pytest.mark.parametrize("schedule", [None, "p=8", "pass2=10", "pass2=13;order=given",
+                                      "threads=512", "pass2=1", "pass2=2;order=given"])
+def test_queue_all_lengths(schedule):
+    g = np.random.default_rng(5)
+    sizes = np.array([1 << e for e in list(range(0, 17)) * 2])
+    g.shuffle(sizes)
+    items, ft = check_queue(sizes, schedule)
+    simulate(items, ft, 4, g)
+
+
+def test_queue_large_lengths():
+    sizes = [1 << 24, 1 << 20, 1 << 17, 8, 1]
+    items, ft = check_queue(sizes)
+    simulate(items, ft, 2, np.random.default_rng(1))
+
+
+def test_queue_errors():
+    for sizes, code in (([3], capi.FFT_ERR_UNSUPPORTED_SIZE), ([1 << 25], capi.FFT_ERR_UNSUPPORTED_SIZE)):
+        with pytest.raises(capi.FFTError) as ei:
+            capi.fft_describe_many(sizes)
+        assert ei.value.status == code
+    for bad in ("p=7", "threads=100", "pass2=0", "pass2=14", "order=random", "x=1"):
+        with pytest.raises(capi.FFTError) as ei:
+            capi.fft_describe_many([256], schedule=bad)
+        assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT, bad
