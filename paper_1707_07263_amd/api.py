@@ -12,7 +12,7 @@ import threading
 
 import torch
 
-from . import capi
+from . import autotune, capi
 
 _DT = {torch.complex64: capi.FFT_C64, torch.float16: capi.FFT_C16F, torch.bfloat16: capi.FFT_C16BF}
 
@@ -57,6 +57,8 @@ def get_plan(shape, batch: int, dtype: int, direction: int, *, scale=None,
              schedule: str | None = None, device=None) -> Plan:
     """Cached plan for `batch` transforms of `shape` (1 or 2 dims)."""
     dev = torch.cuda.current_device() if device is None else torch.device(device).index
+    if schedule is None:
+        schedule = autotune.schedule_for(shape, batch, dtype)
     key = ("plan", tuple(int(s) for s in shape), int(batch), dtype, direction, scale, schedule, dev)
     with _lock:
         p = _cache.get(key)
@@ -73,6 +75,8 @@ def get_plan(shape, batch: int, dtype: int, direction: int, *, scale=None,
 def get_many_plan(sizes, dtype: int, direction: int, *, scale=None, schedule=None,
                   device=None) -> Plan:
     dev = torch.cuda.current_device() if device is None else torch.device(device).index
+    if schedule is None:
+        schedule = autotune.many_schedule_for(sizes, dtype)
     key = ("many", tuple(int(s) for s in sizes), dtype, direction, scale, schedule, dev)
     with _lock:
         p = _cache.get(key)

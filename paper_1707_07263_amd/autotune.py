@@ -1,0 +1,297 @@
+"""Schedule autotuner for the FFT plans.
+
+A plan's schedule is a string understood by fft_plan_ex / fft_plan_many_ex
+(the split N1, and the kernel variant of each pass; or, for batched uneven
+sizes, points per lane, workgroup size, two-pass threshold and queue order).
+The tuner times candidates on the GPU with the library's own per-launch HIP
+events and keeps the fastest:
+
+* one-pass and 2-D plans: every compiled variant of each pass, one pass at a
+  time with the others fixed (coordinate descent, two sweeps);
+* 1-D two-pass plans: every split N1 x N2 whose halves have variants, then
+  coordinate descent over the first- and second-pass variants of the best
+  splits;
+* batched plans: the cross product of the compiled persistent-kernel
+  variants, two-pass thresholds and queue orders.
+
+Inputs rotate over >= 1 GiB of buffers so each timed launch reads HBM, not
+the Infinity Cache.  Results go to a JSON cache keyed by GPU architecture and
+problem; `schedule_for` / `many_schedule_for` look them up for the API.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import threading
+import time
+
+from . import capi
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE_PATH = os.environ.get("MI355FFT_TUNE_CACHE", os.path.join(HERE, "tuned_schedules.json"))
+ARCH = "gfx950"
+_lock = threading.Lock()
+_cache = None
+
+ROLE_ROW, ROLE_A, ROLE_COL = 0, 1, 2
+
+
+def _load_cache() -> dict:
+    global _cache
+    if _cache is None:
+        try:
+            with open(CACHE_PATH) as f:
+                _cache = json.load(f)
+        except (OSError, ValueError):
+            _cache = {}
+    return _cache
+
+
+def _key(kind, shape, batch, dtype):
+    return f"{ARCH}|{kind}|{'x'.join(str(int(s)) for s in shape)}|{int(batch)}|{int(dtype)}"
+
+
+def _many_key(sizes, dtype):
+    import hashlib
+    h = hashlib.sha1(",".join(str(int(s)) for s in sizes).encode()).hexdigest()[:16]
+    return f"{ARCH}|many|{len(sizes)}|{h}|{int(dtype)}"
+
+
+def schedule_for(shape, batch, dtype):
+    """Tuned schedule string for a strided plan, or None."""
+    with _lock:
+        e = _load_cache().get(_key("plan", shape, batch, dtype))
+    return None if e is None else e["schedule"]
+
+
+def many_schedule_for(sizes, dtype):
+    with _lock:
+        e = _load_cache().get(_many_key(sizes, dtype))
+    return None if e is None else e["schedule"]
+
+
+def save(entries: dict, path: str | None = None) -> None:
+    path = path or CACHE_PATH
+    with _lock:
+        c = dict(_load_cache())
+        c.update(entries)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(c, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+        global _cache
+        _cache = c
+
+
+# ---------------------------------------------------------------------------
+# timing
+# ---------------------------------------------------------------------------
+class _Buffers:
+    """Rotating input/output sets of >= 1 GiB in total."""
+
+    def __init__(self, elems: int, esize: int, torch):
+        self.torch = torch
+        set_bytes = 2 * elems * esize
+        self.n = max(2, math.ceil((1 << 30) / set_bytes))
+        words = elems * esize // 4
+        self.sets = [(torch.randn(words, device="cuda"), torch.empty(words, device="cuda"))
+                     for _ in range(self.n)]
+
+    def ptrs(self, i):
+        a, b = self.sets[i % self.n]
+        return a.data_ptr(), b.data_ptr()
+
+
+def _time_handle(h, bufs, reps, warm=2):
+    import torch
+    st = torch.cuda.current_stream().cuda_stream
+    for i in range(warm):
+        capi.fft_exec(h, *bufs.ptrs(i), st)
+    torch.cuda.synchronize()
+    capi.fft_profile_enable(h, reps)
+    for i in range(reps):
+        capi.fft_exec(h, *bufs.ptrs(warm + i), st)
+    torch.cuda.synchronize()
+    capi.fft_profile_collect(h)
+    info = capi.fft_plan_info(h)
+    per = []
+    for p in range(info["passes"]):
+        ms, n = capi.fft_profile_read(h, p)
+        per.append(1e3 * ms / max(n, 1))
+    capi.fft_profile_enable(h, 0)
+    return per, info
+
+
+def _variants():
+    out = []
+    for i in range(capi.fft_variant_count()):
+        d = capi.fft_variant_describe(i)
+        d["name"] = capi.fft_variant_name(i)
+        out.append(d)
+    return out
+
+
+def _time_schedule(shape, batch, dtype, sched, bufs, reps):
+    try:
+        h = capi.fft_plan_ex(list(shape), batch, len(shape), dtype, capi.FFT_FORWARD, sched)
+    except capi.FFTError:
+        return None
+    try:
+        per, info = _time_handle(h, bufs, reps)
+    finally:
+        capi.fft_destroy(h)
+    return per, info
+
+
+def tune_plan(shape, batch, dtype=capi.FFT_C64, reps=10, verbose=False):
+    """Tune a strided plan; returns (schedule string, per-pass microseconds)."""
+    import torch
+    shape = [int(s) for s in shape]
+    n = 1
+    for s in shape:
+        n *= s
+    esize = 8 if dtype == capi.FFT_C64 else 4
+    bufs = _Buffers(n * batch, esize, torch)
+    var = [v for v in _variants() if v["dtype"] == dtype]
+
+    def names(role, L):
+        return [v["name"] for v in var if v["role"] == role and v["L"] == L]
+
+    results = []
+
+    def run(sched):
+        r = _time_schedule(shape, batch, dtype, sched, bufs, reps)
+        if r is None:
+            return None
+        per, info = r
+        results.append((sum(per), sched, per, info["pass_variant"]))
+        if verbose:
+            print(f"  {sum(per):9.2f} us  {sched}  {['%.1f' % x for x in per]}", flush=True)
+        return sum(per), per, info
+
+    base = run(None)
+    if base is None:
+        raise capi.FFTError(capi.FFT_ERR_UNSUPPORTED_SIZE, "tune_plan")
+    info = base[2]
+    keys = []
+    if len(shape) == 2:
+        if shape[1] > 1:
+            keys.append(("row", ROLE_ROW, shape[1]))
+        if shape[0] > 1:
+            keys.append(("col", ROLE_COL, shape[0]))
+        splits = [None]
+    elif info["passes"] == 1 and shape[0] > 1:
+        keys.append(("single", ROLE_ROW, shape[0]))
+        splits = [None]
+    elif info["passes"] == 2:
+        lg = int(math.log2(shape[0]))
+        splits = [1 << a for a in range(6, 13) if 6 <= lg - a <= 12]
+    else:
+        return "", base[1]
+
+    def descend(prefix, keys, start):
+        cur = dict(start)
+        for _ in range(2):
+            for key, role, L in keys:
+                best = None
+                for nm in names(role, L):
+                    trial = dict(cur)
+                    trial[key] = nm
+                    s = ";".join(f"{k}={v}" for k, v in trial.items())
+                    r = run(s)
+                    if r is not None and (best is None or r[0] < best[0]):
+                        best = (r[0], nm)
+                if best is not None:
+                    cur[key] = best[1]
+        return cur
+
+    if splits == [None]:
+        descend("", keys, {})
+    else:
+        # rank splits by their default variants, then refine the two best
+        ranked = []
+        for sp in splits:
+            r = run(f"split={sp}")
+            if r is not None:
+                ranked.append((r[0], sp))
+        ranked.sort()
+        for _, sp in ranked[:2]:
+            N1, N2 = sp, shape[0] // sp
+            descend("", [("a", ROLE_A, N1), ("b", ROLE_COL, N2)], {"split": sp})
+    best = min(results, key=lambda r: r[0])
+    return best[1] or "", best[2]
+
+
+def tune_many(sizes, dtype=capi.FFT_C64, reps=10, verbose=False):
+    """Tune a batched-uneven plan; returns (schedule string, microseconds)."""
+    import torch
+    total = int(sum(int(s) for s in sizes))
+    esize = 8 if dtype == capi.FFT_C64 else 4
+    bufs = _Buffers(total, esize, torch)
+    best = None
+    for P in (8, 16):
+        for threads in (256, 512):
+            max_tile = min(12, int(math.log2(threads * P)))
+            for pass2 in range(max(8, max_tile - 3), max_tile + 2):
+                for order in ("bigfirst", "given"):
+                    s = f"p={P};threads={threads};pass2={pass2};order={order}"
+                    try:
+                        h = capi.fft_plan_many_ex(list(sizes), dtype, capi.FFT_FORWARD, s)
+                    except capi.FFTError:
+                        continue
+                    try:
+                        per, _ = _time_handle(h, bufs, reps)
+                    finally:
+                        capi.fft_destroy(h)
+                    if verbose:
+                        print(f"  {per[0]:9.2f} us  {s}", flush=True)
+                    if best is None or per[0] < best[0]:
+                        best = (per[0], s)
+    return best[1], [best[0]]
+
+
+def tune_and_store(problems, many=(), reps=10, path=None, verbose=True):
+    """Tune a list of (shape, batch, dtype) and of (sizes, dtype); store."""
+    entries = {}
+    for shape, batch, dtype in problems:
+        t0 = time.time()
+        s, per = tune_plan(shape, batch, dtype, reps, verbose)
+        entries[_key("plan", shape, batch, dtype)] = {"schedule": s, "us": per,
+                                                      "tuned_s": round(time.time() - t0, 1)}
+        if verbose:
+            print(f"tuned {shape} x{batch} dtype {dtype}: {s} {per}", flush=True)
+    for sizes, dtype in many:
+        s, per = tune_many(sizes, dtype, reps, verbose)
+        entries[_many_key(sizes, dtype)] = {"schedule": s, "us": per, "count": len(sizes)}
+        if verbose:
+            print(f"tuned many({len(sizes)}) dtype {dtype}: {s} {per}", flush=True)
+    save(entries, path)
+    return entries
+
+
+def standard_problems():
+    """The workloads this package is benchmarked on (1-D 2^10 and 2^20, 2-D
+    4096^2, batched 2^16, batched uneven sizes in three storage types)."""
+    from . import workloads
+    plans = [([1024], 1, capi.FFT_C64), ([1024], 32768, capi.FFT_C64),
+             ([1 << 20], 16, capi.FFT_C64), ([4096, 4096], 1, capi.FFT_C64),
+             ([1 << 16], 64, capi.FFT_C64)]
+    sizes = workloads.uneven_sizes(512, 8, 16, seed=3)
+    many = [(list(int(s) for s in sizes), dt) for dt in (capi.FFT_C64, capi.FFT_C16F, capi.FFT_C16BF)]
+    return plans, many
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="tune the standard workloads and write the cache")
+    ap.add_argument("--out", default=CACHE_PATH)
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--only", choices=["plans", "many", "all"], default="all")
+    args = ap.parse_args()
+    plans, many = standard_problems()
+    if args.only == "plans":
+        many = []
+    if args.only == "many":
+        plans = []
+    tune_and_store(plans, many, reps=args.reps, path=args.out)
