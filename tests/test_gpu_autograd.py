@@ -25,7 +25,7 @@ def row_loss_fp64(x_row, w_row):
     return float(np.sum((w_row * np.abs(X)) ** 2))
 
 
-def test_config5_gradient(dev):
+def test_autograd_64x65536_weighted_power_loss(dev):
     B, N = 64, 1 << 16
     x, w, coords = workloads.autograd_case(B, N, seed=4, probes=32)
     xc = x.astype(np.complex64)
@@ -43,7 +43,7 @@ def test_config5_gradient(dev):
     w64 = wf.astype(np.float64)
     ga = 2.0 * oracle.adjoint(w64 ** 2 * oracle.fft(x64))
     err = np.linalg.norm(g - ga) / np.linalg.norm(ga)
-    print(f"config5 analytic gradient rel-L2 {err:.3e}")
+    print(f"64 x 2^16 analytic gradient rel-L2 {err:.3e}")
     assert err <= 5e-5, err
 
     # FP64 central differences of the affected row's loss, h = 1e-6
@@ -63,7 +63,7 @@ def test_config5_gradient(dev):
             bound = 1e-4 * max(abs(gj), rms)
             worst = max(worst, abs(d - gj) / bound)
             assert abs(d - gj) <= bound, (b, j, part, d, gj)
-    print(f"config5 finite differences: worst |fd - g| / bound = {worst:.3f}")
+    print(f"64 x 2^16 finite differences: worst |fd - g| / bound = {worst:.3f}")
 
 
 def test_adjoint_dot_product(dev):

@@ -60,13 +60,16 @@ def report(name, sizes, errs):
     print("\n".join(lines))
 
 
-def test_config4_complex64(dev):
+@pytest.mark.parametrize("which", ["built-in", "tuned"])
+def test_uneven_512_complex64(dev, which):
+    from paper_1707_07263_amd import autotune
     sizes, packed = workloads.uneven_batch(512, 8, 16, seed=3)
+    sched = autotune.many_schedule_for(sizes, capi.FFT_C64) if which == "tuned" else None
     xc = packed.astype(np.complex64)
-    got = run_many_c64(xc, sizes, dev)
+    got = run_many_c64(xc, sizes, dev, schedule=sched)
     ref = oracle.fft_many(xc, sizes)
     errs = per_transform_errors(got, ref, sizes)
-    report("config4 complex64", sizes, errs)
+    report("512 uneven complex64", sizes, errs)
     tol = 1e-6 * np.log2(sizes.astype(np.float64))
     assert np.all(errs <= tol), float((errs / tol).max())
     inv = run_many_c64(got, sizes, dev, inverse=True)
@@ -75,14 +78,16 @@ def test_config4_complex64(dev):
 
 
 @pytest.mark.parametrize("dt", ["f16", "bf16"])
-def test_config4_16bit(dev, dt):
+def test_uneven_512_16bit(dev, dt):
     code, tname = DT16[dt]
     tdt = getattr(torch, tname)
     sizes, packed = workloads.uneven_batch(512, 8, 16, seed=3)
     xq = quantised(packed, tdt)                      # the values the GPU actually holds
     xt = to_gpu_16(packed, dev, tdt)
     out = torch.empty_like(xt)
-    h = capi.fft_plan_many(list(sizes), code, capi.FFT_FORWARD)
+    from paper_1707_07263_amd import autotune
+    h = capi.fft_plan_many_ex(list(sizes), code, capi.FFT_FORWARD,
+                              autotune.many_schedule_for(sizes, code))
     try:
         capi.fft_exec(h, xt.data_ptr(), out.data_ptr(), torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
@@ -91,11 +96,11 @@ def test_config4_16bit(dev, dt):
     got = from_gpu_16(out)
     ref = oracle.fft_many(xq, sizes)
     errs = per_transform_errors(got, ref, sizes)
-    report(f"config4 {dt} (vs oracle on the quantised input)", sizes, errs)
+    report(f"512 uneven {dt} (vs oracle on the quantised input)", sizes, errs)
     assert errs.max() <= TOL16[dt], float(errs.max())
     # end-to-end error against the unquantised input, reported only
     e2e = per_transform_errors(got, oracle.fft_many(packed, sizes), sizes)
-    print(f"config4 {dt} end-to-end vs unquantised input: max {e2e.max():.3e}")
+    print(f"512 uneven {dt} end-to-end vs unquantised input: max {e2e.max():.3e}")
 
 
 @pytest.mark.parametrize("schedule", [None, "p=8", "pass2=10", "pass2=13;order=given",

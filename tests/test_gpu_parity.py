@@ -87,23 +87,45 @@ def test_two_pass_all_splits(dev, split):
     check_1d(x, n, True, dev, schedule=f"split={split}")
 
 
-def test_config1_n1024(dev):
+@pytest.mark.parametrize("which", ["built-in", "tuned"])
+def test_n1024_uniform_single(dev, which):
     # 1-D N=1024, batch 1, complex64, re/im ~ U[-1,1] seed 0; tolerance 1e-5
     x = workloads.uniform_1d(1024, 1, seed=0)
-    err = check_1d(x, 1024, False, dev)
+    err = check_1d(x, 1024, False, dev, schedule=tuned([1024], 1) if which == "tuned" else None)
     assert err.max() <= 1e-5
 
 
-def test_config2_n2p20_forward_inverse(dev):
-    # N = 2^20, batch 16, N(0,1) seed 1: forward, then inverse of the GPU output
+def test_n1024_batch32768_tuned(dev):
+    # the 1024-point throughput shape under its tuned schedule
+    x = workloads.uniform_1d(1024, 32768, seed=0)
+    err = check_1d(x, 1024, False, dev, schedule=tuned([1024], 32768))
+    assert err.max() <= 1e-5
+
+
+def test_n2p16_batch64_tuned(dev):
+    x = workloads.normal_batch(1 << 16, 64, seed=4)
+    check_1d(x, 1 << 16, False, dev, schedule=tuned([1 << 16], 64))
+    check_1d(x, 1 << 16, True, dev, schedule=tuned([1 << 16], 64))
+
+
+def tuned(shape, batch):
+    from paper_1707_07263_amd import autotune
+    return autotune.schedule_for(shape, batch, capi.FFT_C64)
+
+
+@pytest.mark.parametrize("which", ["built-in", "tuned"])
+def test_n2p20_batch16_forward_inverse(dev, which):
+    # N = 2^20, batch 16, N(0,1) seed 1: forward, then inverse of the GPU
+    # output; "tuned" is the schedule the benchmark times
     n, b = 1 << 20, 16
+    sched = tuned([n], b) if which == "tuned" else None
     x = workloads.normal_batch(n, b, seed=1)
     xc = x.astype(np.complex64)
-    fwd = run_c64(xc, [n], dev=dev)
+    fwd = run_c64(xc, [n], schedule=sched, dev=dev)
     ref = oracle.fft(xc)
     e1 = rel_l2_rows(fwd, ref, n)
     assert e1.max() <= 2.0e-5, float(e1.max())
-    inv = run_c64(fwd, [n], inverse=True, dev=dev)
+    inv = run_c64(fwd, [n], inverse=True, schedule=sched, dev=dev)
     ref_inv = oracle.ifft(fwd)
     e2 = rel_l2_rows(inv, ref_inv, n)
     assert e2.max() <= 2.0e-5, float(e2.max())
@@ -113,10 +135,12 @@ def test_config2_n2p20_forward_inverse(dev):
     assert e1.max() < 1e-6, float(e1.max())
 
 
-def test_config3_2d_4096_image(dev):
+@pytest.mark.parametrize("which", ["built-in", "tuned"])
+def test_2d_4096x4096_speckle_image(dev, which):
     z = workloads.speckle_image(4096, 4096, seed=2)
     zc = z.astype(np.complex64)
-    got = run_c64(zc, [4096, 4096], dev=dev)
+    sched = tuned([4096, 4096], 1) if which == "tuned" else None
+    got = run_c64(zc, [4096, 4096], schedule=sched, dev=dev)
     ref = oracle.fft2(zc)
     err = rel_l2_rows(got.reshape(1, -1), ref.reshape(1, -1), 4096 * 4096)
     assert err.max() <= 2.4e-5, float(err.max())

@@ -73,7 +73,7 @@ def simulate(items, first_tiles, workers, rng):
     return steps
 
 
-def test_config4_queue():
+def test_uneven_512_queue():
     sizes = workloads.uneven_sizes(512, 8, 16, seed=3)
     items, ft = check_queue(sizes)
     rng = np.random.default_rng(0)
