@@ -37,25 +37,26 @@ def build(force: bool = False) -> str:
     return _LIB_PATH
 
 
+def _declare(lib):
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_int64
+    lib.oracle_fft1d.argtypes = [dp, i64, i64, ctypes.c_int, ctypes.c_double]
+    lib.oracle_fft2d.argtypes = [dp, i64, i64, i64, ctypes.c_int, ctypes.c_double]
+    lib.oracle_fft_many.argtypes = [dp, ctypes.POINTER(i64), i64, ctypes.c_int, ctypes.c_double]
+    lib.oracle_dft_direct.argtypes = [dp, dp, i64, ctypes.c_int]
+    lib.oracle_max_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    for f in (lib.oracle_fft1d, lib.oracle_fft2d, lib.oracle_fft_many, lib.oracle_dft_direct):
+        f.restype = ctypes.c_int
+    return lib
+
+
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        lib = ctypes.CDLL(_LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        i64 = ctypes.c_int64
-        lib.oracle_fft1d.argtypes = [dp, i64, i64, ctypes.c_int, ctypes.c_double]
-        lib.oracle_fft2d.argtypes = [dp, i64, i64, i64, ctypes.c_int, ctypes.c_double]
-        lib.oracle_fft_many.argtypes = [dp, ctypes.POINTER(i64), i64, ctypes.c_int,
-                                        ctypes.c_double]
-        lib.oracle_dft_direct.argtypes = [dp, dp, i64, ctypes.c_int]
-        lib.oracle_max_threads.restype = ctypes.c_int
-        lib.oracle_set_threads.argtypes = [ctypes.c_int]
-        for f in (lib.oracle_fft1d, lib.oracle_fft2d, lib.oracle_fft_many,
-                  lib.oracle_dft_direct):
-            f.restype = ctypes.c_int
-        _lib = lib
+        _lib = _declare(ctypes.CDLL(_LIB_PATH))
     return _lib
 
 
@@ -143,3 +144,39 @@ def max_threads() -> int:
 
 def set_threads(n: int) -> None:
     _load().oracle_set_threads(int(n))
+
+
+class Oracle:
+    """The same functions bound to another build of oracle.c (used by the
+    tests that plant mistakes in a copy of the source and check that the
+    pins catch them)."""
+
+    def __init__(self, lib_path: str):
+        self._lib = _declare(ctypes.CDLL(lib_path))
+
+    def _swap(self, fn, *a, **k):
+        global _lib
+        saved = _lib
+        _lib = self._lib
+        try:
+            return fn(*a, **k)
+        finally:
+            _lib = saved
+
+    def fft(self, *a, **k):
+        return self._swap(fft, *a, **k)
+
+    def ifft(self, *a, **k):
+        return self._swap(ifft, *a, **k)
+
+    def adjoint(self, *a, **k):
+        return self._swap(adjoint, *a, **k)
+
+    def fft2(self, *a, **k):
+        return self._swap(fft2, *a, **k)
+
+    def fft_many(self, *a, **k):
+        return self._swap(fft_many, *a, **k)
+
+    def dft_direct(self, *a, **k):
+        return self._swap(dft_direct, *a, **k)

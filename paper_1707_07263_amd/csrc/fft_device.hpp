@@ -198,6 +198,7 @@ struct PassArgs {
   float scale;                  // applied to every output value
   int32_t conj_in, conj_out;    // inverse direction: conj on first load / last store
   int32_t xcd_remap;            // 1: consecutive tiles on one XCD
+  int32_t grid;                 // persistent kernels: workgroups launched (host sets)
 };
 
 // Map a workgroup id to a tile so that tiles t, t+1, ... run on the same XCD
@@ -206,6 +207,41 @@ __device__ __forceinline__ int64_t tile_of(int64_t b, int64_t n, int remap) {
   if (!remap || (n & 7)) return b;
   return (b & 7) * (n >> 3) + (b >> 3);
 }
+
+// Workgroup barrier that orders LDS accesses only (fences scoped to the
+// "local" address space): global loads issued before it stay in flight, which
+// is what lets the persistent kernel prefetch the next tile across the
+// exchanges of the current one.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Stage twiddles staged in LDS: the same entries as the global table, with
+// each k-row of R factors padded to R + 2 so that lanes reading different
+// rows with 16-byte loads start on different banks.
+template <int L, int P> struct TwLds {
+  using S = Sched<L, P>;
+  __host__ __device__ static constexpr int rp(int s) { return S::radix(s) >= 4 ? S::radix(s) + 2 : S::radix(s); }
+  __host__ __device__ static constexpr int off(int s) {
+    return s <= 1 ? 0 : off(s - 1) + S::ns(s - 1) * rp(s - 1);
+  }
+  static constexpr int SIZE = off(S::S) > 0 ? off(S::S) : 1;
+  // cooperative copy from the global table (entries tw[S::off(s) + k*R + r])
+  __device__ __forceinline__ static void copy(float2* dst, const float2* __restrict__ src, int tid, int nt) {
+    for (int i = tid; i < S::TW; i += nt) {
+      int s = 1;
+#pragma unroll
+      for (int q = 2; q < S::S; ++q)
+        if (i >= S::off(q)) s = q;
+      const int R = S::radix(s);
+      const int loc = i - S::off(s);
+      const int k = loc / R, r = loc % R;
+      dst[off(s) + k * rp(s) + r] = src[i];
+    }
+  }
+};
 
 // ---------------------------------------------------------------------------
 // LDS exchange between two stages.  Lane (m, t) holds the previous stage's
@@ -227,29 +263,29 @@ __device__ __forceinline__ void exchange(float2* v, void* ldsv, int m, int m2, i
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < R; ++r) lds[LY::idx(m, o0[b] + r * NS)] = v[b + r * NB];
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int q = 0; q < PP; ++q) v[q] = lds[LY::idx(m2, t2 + q * T)];
-    __syncthreads();
+    lds_barrier();
   } else {
     float* lds = reinterpret_cast<float*>(ldsv);
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < R; ++r) lds[LY::idx(m, o0[b] + r * NS)] = v[b + r * NB].x;
-    __syncthreads();
+    lds_barrier();
     // the real parts are dead once written: reuse their registers
 #pragma unroll
     for (int q = 0; q < PP; ++q) v[q].x = lds[LY::idx(m2, t2 + q * T)];
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < R; ++r) lds[LY::idx(m, o0[b] + r * NS)] = v[b + r * NB].y;
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int q = 0; q < PP; ++q) v[q].y = lds[LY::idx(m2, t2 + q * T)];
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -265,7 +301,7 @@ __device__ __forceinline__ void exchange(float2* v, void* ldsv, int m, int m2, i
 // Stages are unrolled by compile-time recursion so that every radix, span
 // and register index is a constant.
 // ---------------------------------------------------------------------------
-template <int L, int P, int EX, int s>
+template <int L, int P, int EX, int s, int TWP = 0>
 struct Stage {
   using S = Sched<L, P>;
   static constexpr int T = S::T;
@@ -285,7 +321,9 @@ struct Stage {
 #pragma unroll
       for (int r = 0; r < R; ++r) x[r] = v[b + r * NB];
       if constexpr (s > 0) {
-        const float2* tw = twt + S::off(s) + k * R;
+        // TWP 0: global table; TWP 1: LDS copy with padded rows
+        const float2* tw = TWP == 0 ? twt + S::off(s) + k * R
+                                    : twt + TwLds<L, P>::off(s) + k * TwLds<L, P>::rp(s);
 #pragma unroll
         for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[r]);
       }
@@ -297,19 +335,19 @@ struct Stage {
       exchange<L, PP, EX, R, NS>(v, lds, m, m_st, t_st, o0);
       m = m_st;
       t = t_st;
-      Stage<L, P, EX, s + 1>::run(v, lds, m, t, m_st, t_st, twt);
+      Stage<L, P, EX, s + 1, TWP>::run(v, lds, m, t, m_st, t_st, twt);
     }
   }
 };
 
-template <int L, int P, int W, int EX>
+template <int L, int P, int W, int EX, int TWP = 0>
 __device__ __forceinline__ void run_stages(float2* v, void* lds, int& m, int& t,
                                            int m_st, int t_st, bool remap,
                                            const float2* __restrict__ twt) {
   using S = Sched<L, P>;
   constexpr int T = S::T;
   constexpr int PP = S::PP;
-  Stage<L, P, EX, 0>::run(v, lds, m, t, m_st, t_st, twt);
+  Stage<L, P, EX, 0, TWP>::run(v, lds, m, t, m_st, t_st, twt);
   if constexpr (S::S == 1) {
     if (remap) {
       // one-stage transform whose load and store mappings differ: transpose
@@ -408,6 +446,112 @@ k_strip(PassArgs a) {
         store_c(dst + q * step, y);
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent, software-pipelined strip pass.  One workgroup per CU walks the
+// tiles tile = blockIdx.x, + gridDim.x, ...; while it computes and stores one
+// tile, the loads of its next tile (data, and for the split's first pass the
+// twiddle inputs) are already in flight, so memory transfer overlaps the
+// butterflies instead of alternating with them.  Everything read between
+// issuing a prefetch and consuming it comes from LDS (the stage twiddles are
+// copied there once), since waiting on any later global load would also wait
+// for the prefetch.  Same lane mappings, stages and outputs as k_strip.
+// ---------------------------------------------------------------------------
+template <int L, int P, int W, int EX, bool TWID>
+__host__ __device__ constexpr int pipe_lds_entries() {
+  return (EX == 0 ? W * LdsLayout<L>::LS : (W * LdsLayout<L>::LS + 1) / 2) + TwLds<L, P>::SIZE +
+         (TWID ? W * Sched<L, P>::PP : 0);
+}
+
+template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS>
+__global__ void __launch_bounds__((W * Sched<L, P>::T), 1)
+k_pipe(PassArgs a) {
+  using S = Sched<L, P>;
+  using LY = LdsLayout<L>;
+  constexpr int T = S::T;
+  constexpr int PP = S::PP;
+  constexpr int NT = W * T;
+  constexpr int XN = EX == 0 ? W * LY::LS : (W * LY::LS + 1) / 2;
+  __shared__ float2 lds[pipe_lds_entries<L, P, W, EX, TWID>()];
+  float2* xch = lds;
+  float2* twl = lds + XN;
+  float2* rowl = lds + XN + TwLds<L, P>::SIZE;
+
+  const int tid = threadIdx.x;
+  const int m_ld = LOADM ? tid % W : tid / T;
+  const int t_ld = LOADM ? tid / W : tid % T;
+  const int m_st = STOREM ? tid % W : tid / T;
+  const int t_st = STOREM ? tid / W : tid % T;
+  const uint32_t sgn_in = a.conj_in ? 0x80000000u : 0u;
+  const uint32_t sgn_out = a.conj_out ? 0x80000000u : 0u;
+
+  TwLds<L, P>::copy(twl, a.tw, tid, NT);
+
+  // registers of the prefetched tile
+  float2 vn[PP];
+  float2 rown = make_float2(1.f, 0.f), lon = make_float2(1.f, 0.f), hin = make_float2(1.f, 0.f);
+  auto prefetch = [&](int64_t tl) {
+    const int64_t bat = tl / a.tiles_per_batch;
+    const int line0 = (int)(tl - bat * a.tiles_per_batch) * W;
+    const TS* src = reinterpret_cast<const TS*>(a.in) + bat * a.in_batch +
+                    (int64_t)min(line0 + m_ld, a.lines - 1) * a.in_line + (int64_t)t_ld * a.in_elem;
+    const int64_t step = (int64_t)T * a.in_elem;
+#pragma unroll
+    for (int q = 0; q < PP; ++q) vn[q] = load_c(src + q * step);
+    if (TWID) {
+      // this tile's step rows W_N^{line*q*T} (one entry per lane) and the
+      // lane's base W_N^{line*t}
+      if (tid < W * PP)
+        rown = a.tw_step[(int64_t)min(line0 + tid / PP, a.lines - 1) * PP + (tid % PP)];
+      const uint32_t jb = (uint32_t)min(line0 + m_st, a.lines - 1) * (uint32_t)t_st;
+      lon = a.tw_lo[jb & (uint32_t)a.tw_mask];
+      hin = a.tw_hi[jb >> a.tw_shift];
+    }
+  };
+  static_assert(!TWID || W * PP <= NT, "one step-row entry per lane");
+
+  int64_t tile = blockIdx.x;
+  if (tile < a.total_tiles) prefetch(tile);
+  lds_barrier();  // stage twiddles visible
+  for (; tile < a.total_tiles; tile += gridDim.x) {
+    float2 v[PP];
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+      v[q] = vn[q];
+      v[q].y = __uint_as_float(__float_as_uint(v[q].y) ^ sgn_in);
+    }
+    float2 tw_base = make_float2(1.f, 0.f);
+    if (TWID) {
+      if (tid < W * PP) rowl[tid] = rown;
+      tw_base = cmul(hin, lon);
+    }
+    const int64_t bat = tile / a.tiles_per_batch;
+    const int line0 = (int)(tile - bat * a.tiles_per_batch) * W;
+    const int64_t next = tile + gridDim.x;
+    if (next < a.total_tiles) prefetch(next);
+
+    int m = m_ld, t = t_ld;
+    run_stages<L, P, W, EX, 1>(v, xch, m, t, m_st, t_st, LOADM != STOREM, twl);
+    if (TWID) lds_barrier();  // step rows visible (also when no exchange ran)
+
+    const int line = line0 + m;
+    const bool ok = line < a.lines;
+    TS* dst = reinterpret_cast<TS*>(a.out) + bat * a.out_batch + (int64_t)line * a.out_line +
+              (int64_t)t * a.out_elem;
+    const int64_t step = (int64_t)T * a.out_elem;
+    if (ok) {
+#pragma unroll
+      for (int q = 0; q < PP; ++q) {
+        float2 y = v[q];
+        if (TWID) y = cmul(y, cmul(tw_base, rowl[m * PP + q]));
+        y = cscale(y, a.scale);
+        y.y = __uint_as_float(__float_as_uint(y.y) ^ sgn_out);
+        store_c(dst + q * step, y);
+      }
+    }
+    lds_barrier();  // LDS reads of this tile done before the next one overwrites
   }
 }
 

@@ -51,6 +51,7 @@ const std::vector<Variant>& variants() {
     add_variants_c64_a(add_one);
     add_variants_c64_col(add_one);
     add_variants_c64_col2(add_one);
+    add_variants_c64_pipe(add_one);
     add_variants_c16(add_one);
   });
   return *g_variants;
@@ -586,9 +587,20 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
     fft_destroy(p);
     return rc;
   }
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (e != hipSuccess) {
+    fft_destroy(p);
+    return hip_fail(e);
+  }
   for (size_t i = 0; i < p->sched.passes.size(); ++i) {
     PassSpec& ps = p->sched.passes[i];
     if (!ps.v) continue;
+    if (ps.v->persistent) {
+      // persistent variants launch the resident workgroups only
+      const int per_cu = std::max(1, ps.v->blocks_per_cu());
+      ps.args.grid = (int32_t)std::min<int64_t>(ps.args.total_tiles, (int64_t)per_cu * cus);
+    }
     ps.args.tw = p->d_tables + stage_off[i];
     if (ps.v->role == ROLE_SPLIT_A) {
       ps.args.tw_lo = p->d_tables + lo_off;

@@ -104,16 +104,56 @@ def c16_set():
     return out
 
 
-def name(role, L, P, W, ex, dt):
-    return f"{role}{L}p{min(P, L)}w{W}{'x' if ex else ''}_{dt}"
+def name(role, L, P, W, ex, dt, persist=0):
+    return f"{role}{L}p{min(P, L)}w{W}{'q' if persist else ''}{'x' if ex else ''}_{dt}"
+
+
+def pipe_lds_bytes(L, P, W, ex, twid):
+    pp = min(P, L)
+    xn = W * (L + (L >> 4) + 1) if ex == 0 else (W * (L + (L >> 4) + 1) + 1) // 2
+    # padded stage tables: rows of R + 2 for every stage after the first
+    lg, lp = L.bit_length() - 1, pp.bit_length() - 1
+    S = (lg + lp - 1) // lp if lg > lp else 1
+    first = L >> ((S - 1) * lp)
+    tw, ns = 0, first
+    for _ in range(1, S):
+        tw += ns * ((pp + 2) if pp >= 4 else pp)
+        ns *= pp
+    return 8 * (xn + max(tw, 1) + (W * pp if twid else 0))
+
+
+def pipe_set():
+    """Persistent pipelined variants: one workgroup of 256..1024 lanes per CU."""
+    out = []
+    for role in ("a", "c", "r"):
+        for lg in range(8, 13):
+            L = 1 << lg
+            for P in (16, 32):
+                if P == 32 and L > 1024:
+                    continue
+                for W in ((1, 2, 4) if role == "r" else (8, 16, 32)):
+                    for ex in (0, 1):
+                        t = threads(L, P, W)
+                        if t < 256 or t > 1024:
+                            continue
+                        if role == "a" and W * min(P, L) > t:
+                            continue
+                        if pipe_lds_bytes(L, P, W, ex, role == "a") > LDS_MAX:
+                            continue
+                        if ex and pipe_lds_bytes(L, P, W, 0, role == "a") <= LDS_MAX:
+                            continue
+                        out.append((role, L, P, W, ex))
+    return out
 
 
 def emit(fname, func, items):
     lines = ['#include "variants.hpp"', "", "namespace mfft {", "",
              f"void {func}(void (*add)(const Variant&)) {{"]
-    for role, L, P, W, ex, dt in items:
-        lines.append(f'  add(make_variant<{ROLE[role]}, {L}, {P}, {W}, {ex}, {DT[dt]}>'
-                     f'("{name(role, L, P, W, ex, dt)}"));')
+    for it in items:
+        role, L, P, W, ex, dt = it[:6]
+        persist = it[6] if len(it) > 6 else 0
+        lines.append(f'  add(make_variant<{ROLE[role]}, {L}, {P}, {W}, {ex}, {DT[dt]}, {persist}>'
+                     f'("{name(role, L, P, W, ex, dt, persist)}"));')
     lines += ["}", "", "}  // namespace mfft", ""]
     text = "\n".join(lines)
     path = os.path.join(HERE, fname)
@@ -133,6 +173,7 @@ def main():
     for dt in ("f16", "bf16"):
         items += [v + (dt,) for v in c16_set()]
     emit("variants_c16.hip", "add_variants_c16", items)
+    emit("variants_c64_pipe.hip", "add_variants_c64_pipe", [v + ("c64", 1) for v in pipe_set()])
 
 
 if __name__ == "__main__":

@@ -21,7 +21,9 @@ struct Variant {
   int lds_bytes;
   int tw_entries;  // stage-table entries for this (L, P)
   int ex;          // LDS exchange: 0 = (re, im) pairs, 1 = real then imaginary
+  int persistent;  // 1: k_pipe (grid = resident workgroups, tiles walked in a loop)
   LaunchFn launch;
+  int (*blocks_per_cu)();  // persistent variants: resident workgroups per CU
 };
 
 template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS>
@@ -32,12 +34,29 @@ hipError_t launch_strip(const PassArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS>
+hipError_t launch_pipe(const PassArgs& a, hipStream_t s) {
+  constexpr int NT = W * Sched<L, P>::T;
+  const unsigned grid = (unsigned)(a.grid > 0 ? a.grid : a.total_tiles);
+  hipLaunchKernelGGL((k_pipe<L, P, W, LOADM, STOREM, TWID, EX, TS>), dim3(grid), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS>
+int blocks_pipe() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pipe<L, P, W, LOADM, STOREM, TWID, EX, TS>,
+                                                   W * Sched<L, P>::T, 0) != hipSuccess)
+    return 0;
+  return n;
+}
+
 template <typename TS> struct DtOf;
 template <> struct DtOf<float2> { static constexpr int v = DT_C64; };
 template <> struct DtOf<__half2> { static constexpr int v = DT_C16F; };
 template <> struct DtOf<c16bf> { static constexpr int v = DT_C16BF; };
 
-template <int ROLE, int L, int P, int W, int EX, typename TS>
+template <int ROLE, int L, int P, int W, int EX, typename TS, int PERSIST = 0>
 Variant make_variant(const char* name) {
   constexpr int LOADM = ROLE == ROLE_ROW ? 0 : 1;
   constexpr int STOREM = ROLE == ROLE_COL ? 1 : 0;
@@ -50,10 +69,18 @@ Variant make_variant(const char* name) {
   v.threads = W * Sched<L, P>::T;
   v.role = ROLE;
   v.dtype = DtOf<TS>::v;
-  v.lds_bytes = W * LdsLayout<L>::LS * (EX == 0 ? 8 : 4);
   v.tw_entries = Sched<L, P>::TW;
   v.ex = EX;
-  v.launch = &launch_strip<L, P, W, LOADM, STOREM, TWID, EX, TS>;
+  v.persistent = PERSIST;
+  if constexpr (PERSIST) {
+    v.lds_bytes = pipe_lds_entries<L, P, W, EX, TWID>() * 8;
+    v.launch = &launch_pipe<L, P, W, LOADM, STOREM, TWID, EX, TS>;
+    v.blocks_per_cu = &blocks_pipe<L, P, W, LOADM, STOREM, TWID, EX, TS>;
+  } else {
+    v.lds_bytes = W * LdsLayout<L>::LS * (EX == 0 ? 8 : 4);
+    v.launch = &launch_strip<L, P, W, LOADM, STOREM, TWID, EX, TS>;
+    v.blocks_per_cu = nullptr;
+  }
   return v;
 }
 
@@ -62,6 +89,7 @@ void add_variants_c64_row(void (*add)(const Variant&));
 void add_variants_c64_a(void (*add)(const Variant&));
 void add_variants_c64_col(void (*add)(const Variant&));
 void add_variants_c64_col2(void (*add)(const Variant&));
+void add_variants_c64_pipe(void (*add)(const Variant&));
 void add_variants_c16(void (*add)(const Variant&));
 
 // trivial length-1 / copy-scale kernel

@@ -50,11 +50,11 @@ def test_variant_registry(lib):
         d = capi.fft_variant_describe(i)
         assert name not in seen
         seen.add(name)
-        m = re.match(r"([rac])(\d+)p(\d+)w(\d+)(x?)_(c64|f16|bf16)$", name)
+        m = re.match(r"([rac])(\d+)p(\d+)w(\d+)(q?)(x?)_(c64|f16|bf16)$", name)
         assert m, name
         assert int(m.group(2)) == d["L"] and int(m.group(3)) == d["P"] and int(m.group(4)) == d["W"]
         assert {"r": 0, "a": 1, "c": 2}[m.group(1)] == d["role"]
-        assert {"c64": 0, "f16": 1, "bf16": 2}[m.group(6)] == d["dtype"]
+        assert {"c64": 0, "f16": 1, "bf16": 2}[m.group(7)] == d["dtype"]
         assert d["threads"] == d["W"] * d["L"] // d["P"] and d["threads"] <= 1024
     assert capi.fft_variant_name(n) is None
 

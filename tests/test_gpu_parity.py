@@ -294,3 +294,31 @@ def test_error_codes(dev):
         capi.fft_plan_ex([1 << 16], 1, 1, capi.FFT_C64, -1, "a=nonexistent")
     assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT
     capi.fft_destroy(0)  # NULL is a no-op
+
+
+def _variant_names(prefix_filter):
+    from paper_1707_07263_amd import capi as c
+    return [c.fft_variant_name(i) for i in range(c.fft_variant_count())
+            if prefix_filter(c.fft_variant_name(i))]
+
+
+PERSISTENT = sorted(n for n in _variant_names(lambda s: "q" in s.split("_")[0]))
+
+
+@pytest.mark.parametrize("name", PERSISTENT)
+def test_persistent_variants(dev, name):
+    # every persistent (software-pipelined) variant through a plan that uses
+    # it, with more tiles than resident workgroups and a ragged last tile
+    from paper_1707_07263_amd import capi as c
+    i = [c.fft_variant_name(k) for k in range(c.fft_variant_count())].index(name)
+    d = c.fft_variant_describe(i)
+    L = d["L"]
+    if d["role"] == 0:      # one-pass rows
+        n, batch, sched = L, (1 << 22) // L + 3, f"single={name}"
+    elif d["role"] == 1:    # first pass of a split
+        n, batch, sched = L * 512, 5, f"split={L};a={name}"
+    else:                   # strided columns (second pass of a split)
+        n, batch, sched = 512 * L, 5, f"split=512;b={name}"
+    x = workloads.normal_batch(n, batch, seed=L + batch)
+    check_1d(x, n, False, dev, schedule=sched)
+    check_1d(x, n, True, dev, schedule=sched)
