@@ -14,8 +14,10 @@
  * butterfly stages in LDS and registers in one kernel.  Longer transforms
  * are split in global memory as N = N1*N2 (the reducibility of eq. 5) into
  * a pass of N1-point sub-transforms, a twiddle multiply W_N^{n2*k1}, and a
- * pass of N2-point sub-transforms; each pass is one kernel.  Twiddle factors
- * come from sin/cos tables computed once per plan (Sec. 2.3.1).
+ * pass of N2-point sub-transforms; each pass is one kernel.  2-D transforms
+ * with tall columns use three passes (the paper's three-exchange case):
+ * two column sub-passes and a row pass.  Twiddle factors come from sin/cos
+ * tables computed once per plan (Sec. 2.3.1).
  *
  * Data layout: complex values interleaved (re, im), row-major, batch
  * outermost, contiguous, natural order in and out.
@@ -87,6 +89,19 @@ int fft_plan(const int64_t *n, int64_t batch, int dims, int dtype, int direction
  *   item     := 'split=' N1            (1-D two-pass: first-pass length)
  *             | 'a=' variant | 'b=' variant | 'row=' variant | 'col=' variant
  *             | 'single=' variant
+ *             | 'xcd=' 0|1            (1: consecutive tiles run on one XCD)
+ *             | 'col3=' 0|1           (2-D: columns as two sub-passes of sqrt(rows)
+ *                                       points; rows a power of 4, at least 2 columns)
+ *             | 'colt=' variant       (the first of those sub-passes)
+ *             | 'method=' lds|levels  (1-D only.  'levels' is the method the
+ *                                       paper replaces (Sec. 2.2, Fig. 2), kept
+ *                                       for comparison: one radix-2 kernel per
+ *                                       butterfly level, each reading and writing
+ *                                       every point in global memory, ping-ponging
+ *                                       through a plan-owned buffer of batch*N
+ *                                       elements; in place as well, no workspace.
+ *                                       fft_plan_info reports the whole sequence
+ *                                       as one entry "levels_radix2".)
  *   variant  := name as listed by fft_variant_name()
  * FFT_ERR_INVALID_ARGUMENT if the string does not parse or names a variant
  * that cannot run this size.
@@ -115,6 +130,11 @@ int fft_plan_many(const int64_t *sizes, int64_t count, int dtype, int direction,
  *   'pass2=' t         lengths of at least 2^t use two passes (1 <= t <= 1 +
  *                      log2 of the longest one-tile length, which is the default)
  *   'order=' bigfirst|given   order of the work queue
+ *   'lag=' k           0 (default): every first-pass item ahead of every
+ *                      second-pass item; k > 0: the second-pass items of the
+ *                      i-th two-pass transform follow the first-pass items of
+ *                      the (i+k)-th, so its intermediate is read back while it
+ *                      is still in the last-level cache
  * FFT_ERR_INVALID_ARGUMENT for a malformed item or an uncompiled combination.
  * In-place exec (in == out) is refused with FFT_ERR_INPLACE when any length
  * uses two passes.

@@ -34,7 +34,7 @@ ARCH = "gfx950"
 _lock = threading.Lock()
 _cache = None
 
-ROLE_ROW, ROLE_A, ROLE_COL = 0, 1, 2
+ROLE_ROW, ROLE_A, ROLE_COL, ROLE_COL_TW = 0, 1, 2, 3
 
 
 def _load_cache() -> dict:
@@ -175,12 +175,19 @@ def tune_plan(shape, batch, dtype=capi.FFT_C64, reps=10, verbose=False):
         raise capi.FFTError(capi.FFT_ERR_UNSUPPORTED_SIZE, "tune_plan")
     info = base[2]
     keys = []
+    starts = [{}]
     if len(shape) == 2:
         if shape[1] > 1:
             keys.append(("row", ROLE_ROW, shape[1]))
         if shape[0] > 1:
             keys.append(("col", ROLE_COL, shape[0]))
         splits = [None]
+        lg_r = int(math.log2(shape[0]))
+        if lg_r % 2 == 0 and lg_r >= 2 and shape[1] >= 2 and run("col3=1") is not None:
+            # columns as two sub-passes of sqrt(rows) points, tuned separately
+            sq = 1 << (lg_r // 2)
+            keys3 = [("colt", ROLE_COL_TW, sq), ("col", ROLE_COL, sq), ("row", ROLE_ROW, shape[1])]
+            starts = [{"col3": 0}, ({"col3": 1}, keys3)]
     elif info["passes"] == 1 and shape[0] > 1:
         keys.append(("single", ROLE_ROW, shape[0]))
         splits = [None]
@@ -207,7 +214,11 @@ def tune_plan(shape, batch, dtype=capi.FFT_C64, reps=10, verbose=False):
         return cur
 
     if splits == [None]:
-        descend("", keys, {})
+        for st in starts:
+            if isinstance(st, tuple):
+                descend("", st[1], st[0])
+            else:
+                descend("", keys, st)
     else:
         # rank splits by their default variants, then refine the two best
         ranked = []
@@ -248,6 +259,20 @@ def tune_many(sizes, dtype=capi.FFT_C64, reps=10, verbose=False):
                         print(f"  {per[0]:9.2f} us  {s}", flush=True)
                     if best is None or per[0] < best[0]:
                         best = (per[0], s)
+    if best is not None:
+        # queue order: second passes lagging the first passes by k transforms
+        base = best[1]
+        for lag in (1, 2, 4, 8):
+            s = f"{base};lag={lag}"
+            h = capi.fft_plan_many_ex(list(sizes), dtype, capi.FFT_FORWARD, s)
+            try:
+                per, _ = _time_handle(h, bufs, reps)
+            finally:
+                capi.fft_destroy(h)
+            if verbose:
+                print(f"  {per[0]:9.2f} us  {s}", flush=True)
+            if per[0] < best[0]:
+                best = (per[0], s)
     return best[1], [best[0]]
 
 
@@ -288,8 +313,13 @@ if __name__ == "__main__":
     ap.add_argument("--out", default=CACHE_PATH)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--only", choices=["plans", "many", "all"], default="all")
+    ap.add_argument("--match", default=None,
+                    help="tune only the problems whose cache key contains this text")
     args = ap.parse_args()
     plans, many = standard_problems()
+    if args.match:
+        plans = [p for p in plans if args.match in _key("plan", p[0], p[1], p[2])]
+        many = [m for m in many if args.match in _many_key(m[0], m[1])]
     if args.only == "plans":
         many = []
     if args.only == "many":

@@ -199,7 +199,18 @@ struct PassArgs {
   int32_t conj_in, conj_out;    // inverse direction: conj on first load / last store
   int32_t xcd_remap;            // 1: consecutive tiles on one XCD
   int32_t grid;                 // persistent kernels: workgroups launched (host sets)
+  int32_t tw_line_shift;        // inter-pass twiddle uses line >> shift as its row index
+  // row pass of the three-pass 2-D plan: tile t of a batch reads rows
+  // line_map[t*W + m] and writes each row r to its transpose in an S x S
+  // grid of rows, S = 2^tr_shift (pairs (r, r^T) share a tile, so the
+  // permutation happens in place)
+  const int32_t* line_map;
+  int32_t tr_shift;
 };
+
+__device__ __forceinline__ int row_transpose(int r, int sh) {
+  return ((r & ((1 << sh) - 1)) << sh) | (r >> sh);
+}
 
 // Map a workgroup id to a tile so that tiles t, t+1, ... run on the same XCD
 // (workgroups are dealt round-robin to the 8 XCDs, each with its own L2).
@@ -403,11 +414,13 @@ k_strip(PassArgs a) {
   const int m_st = STOREM ? tid % W : tid / T;
   const int t_st = STOREM ? tid / W : tid % T;
 
+  const int tile_in_batch = (int)(tile - bat * a.tiles_per_batch);
   float2 v[PP];
   {
     // lines past the end of a partial strip load a valid line and are not stored
+    const int ln = a.line_map ? a.line_map[tile_in_batch * W + m] : min(line0 + m, a.lines - 1);
     const TS* src = reinterpret_cast<const TS*>(a.in) + bat * a.in_batch +
-                    (int64_t)min(line0 + m, a.lines - 1) * a.in_line + (int64_t)t * a.in_elem;
+                    (int64_t)ln * a.in_line + (int64_t)t * a.in_elem;
     const int64_t step = (int64_t)T * a.in_elem;
     const uint32_t sgn = a.conj_in ? 0x80000000u : 0u;
 #pragma unroll
@@ -421,19 +434,22 @@ k_strip(PassArgs a) {
 
   // epilogue: inter-pass twiddle, scale, conjugate, store
   {
-    const int line = line0 + m;
-    const bool ok = line < a.lines;
+    const int line = a.line_map ? row_transpose(a.line_map[tile_in_batch * W + m], a.tr_shift)
+                                : line0 + m;
+    const bool ok = a.line_map ? true : line < a.lines;
     TS* dst = reinterpret_cast<TS*>(a.out) + bat * a.out_batch + (int64_t)line * a.out_line +
               (int64_t)t * a.out_elem;
     const int64_t step = (int64_t)T * a.out_elem;
-    // inter-pass twiddle W_N^{line*(t + q*T)} = W_N^{line*t} * W_N^{line*q*T}:
-    // one base per lane, and a step row shared by the lanes of a line
+    // inter-pass twiddle W_N^{row*(t + q*T)} = W_N^{row*t} * W_N^{row*q*T}
+    // (row = line >> tw_line_shift): one base per lane, and a step row
+    // shared by the lanes of a line
     float2 tw_base = make_float2(1.f, 0.f);
     const float2* tw_row = a.tw_step;
     if (TWID && ok) {
-      const uint32_t jb = (uint32_t)line * (uint32_t)t;
+      const uint32_t row = (uint32_t)line >> a.tw_line_shift;
+      const uint32_t jb = row * (uint32_t)t;
       tw_base = cmul(a.tw_hi[jb >> a.tw_shift], a.tw_lo[jb & (uint32_t)a.tw_mask]);
-      tw_row = a.tw_step + (int64_t)line * PP;
+      tw_row = a.tw_step + (int64_t)row * PP;
     }
     const uint32_t sgn = a.conj_out ? 0x80000000u : 0u;
     if (ok) {
@@ -495,17 +511,20 @@ k_pipe(PassArgs a) {
   auto prefetch = [&](int64_t tl) {
     const int64_t bat = tl / a.tiles_per_batch;
     const int line0 = (int)(tl - bat * a.tiles_per_batch) * W;
+    const int tib = (int)(tl - bat * a.tiles_per_batch);
+    const int ln = a.line_map ? a.line_map[tib * W + m_ld] : min(line0 + m_ld, a.lines - 1);
     const TS* src = reinterpret_cast<const TS*>(a.in) + bat * a.in_batch +
-                    (int64_t)min(line0 + m_ld, a.lines - 1) * a.in_line + (int64_t)t_ld * a.in_elem;
+                    (int64_t)ln * a.in_line + (int64_t)t_ld * a.in_elem;
     const int64_t step = (int64_t)T * a.in_elem;
 #pragma unroll
     for (int q = 0; q < PP; ++q) vn[q] = load_c(src + q * step);
     if (TWID) {
-      // this tile's step rows W_N^{line*q*T} (one entry per lane) and the
-      // lane's base W_N^{line*t}
+      // this tile's step rows W_N^{row*q*T} (one entry per lane) and the
+      // lane's base W_N^{row*t}, row = line >> tw_line_shift
       if (tid < W * PP)
-        rown = a.tw_step[(int64_t)min(line0 + tid / PP, a.lines - 1) * PP + (tid % PP)];
-      const uint32_t jb = (uint32_t)min(line0 + m_st, a.lines - 1) * (uint32_t)t_st;
+        rown = a.tw_step[(int64_t)((uint32_t)min(line0 + tid / PP, a.lines - 1) >> a.tw_line_shift) * PP +
+                         (tid % PP)];
+      const uint32_t jb = ((uint32_t)min(line0 + m_st, a.lines - 1) >> a.tw_line_shift) * (uint32_t)t_st;
       lon = a.tw_lo[jb & (uint32_t)a.tw_mask];
       hin = a.tw_hi[jb >> a.tw_shift];
     }
@@ -536,8 +555,9 @@ k_pipe(PassArgs a) {
     run_stages<L, P, W, EX, 1>(v, xch, m, t, m_st, t_st, LOADM != STOREM, twl);
     if (TWID) lds_barrier();  // step rows visible (also when no exchange ran)
 
-    const int line = line0 + m;
-    const bool ok = line < a.lines;
+    const int tib = (int)(tile - bat * a.tiles_per_batch);
+    const int line = a.line_map ? row_transpose(a.line_map[tib * W + m], a.tr_shift) : line0 + m;
+    const bool ok = a.line_map ? true : line < a.lines;
     TS* dst = reinterpret_cast<TS*>(a.out) + bat * a.out_batch + (int64_t)line * a.out_line +
               (int64_t)t * a.out_elem;
     const int64_t step = (int64_t)T * a.out_elem;

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "mi355fft.h"
+#include "levels.hpp"
 #include "many.hpp"
 #include "twiddle.hpp"
 #include "variants.hpp"
@@ -103,6 +104,9 @@ struct PassSpec {
   int src = SEL_IN, dst = SEL_OUT;
   int64_t copy_n = 0;          // copy-scale: points
   bool first = false, last = false;
+  int64_t tw_N = 0;            // inter-pass twiddle modulus (0: none)
+  int64_t tw_rows = 0;         // rows of its step table
+  std::vector<int32_t> line_map;  // row pass of the three-pass 2-D plan
 };
 
 struct Schedule {
@@ -110,11 +114,16 @@ struct Schedule {
   int64_t split[2] = {0, 0};
   int64_t points = 0;
   bool inplace_needs_ws = false;
+  // one global-memory kernel per radix-2 level instead of LDS passes
+  bool levels = false;
 };
 
 struct Overrides {
   int64_t split = 0;
-  std::string a, b, row, col, single;
+  int xcd = 0;    // 1: map consecutive tiles to one XCD
+  int col3 = -1;  // 2-D columns in two sub-passes: 1 yes, 0 no, -1 automatic
+  bool levels = false;  // method=levels: the per-level global-memory method
+  std::string a, b, row, col, single, colt;
 };
 
 int parse_schedule(const char* s, Overrides* o) {
@@ -135,7 +144,17 @@ int parse_schedule(const char* s, Overrides* o) {
       long long v = strtoll(val.c_str(), &e, 10);
       if (!e || *e || v < 1) return FFT_ERR_INVALID_ARGUMENT;
       o->split = v;
-    } else if (key == "a") o->a = val;
+    } else if (key == "xcd") {
+      if (val != "0" && val != "1") return FFT_ERR_INVALID_ARGUMENT;
+      o->xcd = val == "1";
+    } else if (key == "col3") {
+      if (val != "0" && val != "1") return FFT_ERR_INVALID_ARGUMENT;
+      o->col3 = val == "1";
+    } else if (key == "method") {
+      if (val != "lds" && val != "levels") return FFT_ERR_INVALID_ARGUMENT;
+      o->levels = val == "levels";
+    } else if (key == "colt") o->colt = val;
+    else if (key == "a") o->a = val;
     else if (key == "b") o->b = val;
     else if (key == "row") o->row = val;
     else if (key == "col") o->col = val;
@@ -161,6 +180,84 @@ int choose(const std::string& name, int role, int L, int dtype, int want_w, int6
 constexpr int kSingleMaxLog2 = 14;  // one-kernel transforms up to 2^14 points
 constexpr int kSplitMinLog2 = 6, kSplitMaxLog2 = 12;
 
+// Columns of length R = Sq*Sq as two in-place column passes (the
+// three-exchange decomposition: the image viewed as [Sq][Sq][C]), then the
+// row pass, which also undoes the digit transposition the second column pass
+// leaves (row k1*Sq + k2 holds frequency k1 + Sq*k2) by swapping each row
+// with its transpose.
+int build_three_pass_2d(int64_t R, int64_t C, int64_t batch, int dtype, const Overrides& ov,
+                      Schedule* outp) {
+  Schedule& S = *outp;
+  const int lgR = ilog2_64(R);
+  if ((lgR & 1) || lgR < 2 || C < 2) return FFT_ERR_INVALID_ARGUMENT;
+  const int64_t Sq = (int64_t)1 << (lgR / 2);
+  if (Sq * C > INT32_MAX || R * batch > INT32_MAX) return FFT_ERR_UNSUPPORTED_SIZE;
+  PassSpec c1, c2, rw;
+  int rc = choose(ov.colt, ROLE_COL_TW, (int)Sq, dtype, 64, C, &c1.v);
+  if (rc) return rc;
+  rc = choose(ov.col, ROLE_COL, (int)Sq, dtype, 64, C, &c2.v);
+  if (rc) return rc;
+  rc = choose(ov.row, ROLE_ROW, (int)C, dtype, 2, R, &rw.v);
+  if (rc) return rc;
+  // row tiles of an even number of rows never split a transpose pair (the
+  // map lists the pairs first, then the diagonal rows), and whole tiles
+  // cover the R rows of an image
+  if (c1.v->W > C || c2.v->W > C || (rw.v->W & 1) || R % rw.v->W) return FFT_ERR_INVALID_ARGUMENT;
+  // pass 1: line (n2, c) at offset n2*C + c, points n1 at stride Sq*C;
+  // times W_R^{n2*k1}, n2 = line >> log2(C)
+  PassArgs& a1 = c1.args;
+  a1.in_batch = a1.out_batch = R * C;
+  a1.in_line = a1.out_line = 1;
+  a1.in_elem = a1.out_elem = Sq * C;
+  a1.lines = (int32_t)(Sq * C);
+  a1.tiles_per_batch = (int32_t)(Sq * C / c1.v->W);
+  a1.total_tiles = (int64_t)a1.tiles_per_batch * batch;
+  a1.tw_shift = (lgR + 1) / 2;
+  a1.tw_mask = (1 << a1.tw_shift) - 1;
+  a1.tw_line_shift = ilog2_64(C);
+  c1.tw_N = R;
+  c1.tw_rows = Sq;
+  c1.src = SEL_IN;
+  c1.dst = SEL_OUT;
+  // pass 2: for each block k1 of Sq rows: line c, points n2 at stride C
+  PassArgs& a2 = c2.args;
+  a2.in_batch = a2.out_batch = Sq * C;
+  a2.in_line = a2.out_line = 1;
+  a2.in_elem = a2.out_elem = C;
+  a2.lines = (int32_t)C;
+  a2.tiles_per_batch = (int32_t)(C / c2.v->W);
+  a2.total_tiles = (int64_t)a2.tiles_per_batch * batch * Sq;
+  c2.src = SEL_OUT;
+  c2.dst = SEL_OUT;
+  // pass 3: rows, each tile a set of rows closed under transposition
+  PassArgs& a3 = rw.args;
+  a3.in_batch = a3.out_batch = R * C;
+  a3.in_line = a3.out_line = C;
+  a3.in_elem = a3.out_elem = 1;
+  a3.lines = (int32_t)R;
+  a3.tiles_per_batch = (int32_t)(R / rw.v->W);
+  a3.total_tiles = (int64_t)a3.tiles_per_batch * batch;
+  a3.tr_shift = lgR / 2;
+  std::vector<int32_t>& mp = rw.line_map;
+  for (int64_t x = 0; x < Sq; ++x)
+    for (int64_t y = x + 1; y < Sq; ++y) {
+      mp.push_back((int32_t)(x * Sq + y));
+      mp.push_back((int32_t)(y * Sq + x));
+    }
+  for (int64_t x = 0; x < Sq; ++x) mp.push_back((int32_t)(x * Sq + x));
+  rw.src = SEL_OUT;
+  rw.dst = SEL_OUT;
+  if (c1.args.total_tiles > INT32_MAX || c2.args.total_tiles > INT32_MAX) return FFT_ERR_UNSUPPORTED_SIZE;
+  S.passes.push_back(c1);
+  S.passes.push_back(c2);
+  S.passes.push_back(rw);
+  S.passes.front().first = true;
+  S.passes.back().last = true;
+  for (PassSpec& ps : S.passes) ps.args.xcd_remap = ov.xcd;
+  return FFT_OK;
+
+}
+
 int build_schedule(const int64_t* n, int64_t batch, int dims, int dtype, const char* sched,
                    Schedule* out) {
   if (!n || batch < 1 || (dims != 1 && dims != 2)) return FFT_ERR_INVALID_ARGUMENT;
@@ -174,6 +271,11 @@ int build_schedule(const int64_t* n, int64_t batch, int dims, int dtype, const c
     if (batch > ((int64_t)1 << 40) / N) return FFT_ERR_UNSUPPORTED_SIZE;
     S.points = N * batch;
     const int l = ilog2_64(N);
+    if (ov.levels && N > 1) {
+      S.levels = true;
+      *out = S;
+      return FFT_OK;
+    }
     if (N == 1) {
       PassSpec p;
       p.copy_n = batch;
@@ -218,6 +320,8 @@ int build_schedule(const int64_t* n, int64_t batch, int dims, int dtype, const c
       a.total_tiles = (int64_t)a.tiles_per_batch * batch;
       a.tw_shift = (l + 1) / 2;
       a.tw_mask = (1 << a.tw_shift) - 1;
+      A.tw_N = N;
+      A.tw_rows = N2;
       A.first = true;
       // pass B: T viewed as [N2][N1]; line k1 (column), point n2; writes
       // X[k1 + N1*k2] in place of its own columns.
@@ -240,10 +344,24 @@ int build_schedule(const int64_t* n, int64_t batch, int dims, int dtype, const c
     }
   } else {
     const int64_t R = n[0], C = n[1];
+    if (ov.levels) return FFT_ERR_INVALID_ARGUMENT;  // 1-D only
     if (!pow2(R) || !pow2(C) || ilog2_64(R) > FFT_MAX_LOG2_2D || ilog2_64(C) > FFT_MAX_LOG2_2D)
       return FFT_ERR_UNSUPPORTED_SIZE;
     if (batch > ((int64_t)1 << 40) / (R * C)) return FFT_ERR_UNSUPPORTED_SIZE;
     S.points = R * C * batch;
+    const int lgR = ilog2_64(R);
+    const bool three = ov.col3 == 1 ? true
+                       : ov.col3 == 0 ? false
+                                      : (lgR >= 12 && C >= 16);
+    if (three) {
+      Schedule S3 = S;
+      int rc3 = build_three_pass_2d(R, C, batch, dtype, ov, &S3);
+      if (rc3 == FFT_OK) {
+        *out = S3;
+        return FFT_OK;
+      }
+      if (ov.col3 == 1) return rc3;  // asked for explicitly: report why not
+    }
     if (C > 1) {
       PassSpec p;
       int rc = choose(ov.row, ROLE_ROW, (int)C, dtype, 64, R * batch, &p.v);
@@ -284,6 +402,7 @@ int build_schedule(const int64_t* n, int64_t batch, int dims, int dtype, const c
     S.passes.front().first = true;
     S.passes.back().last = true;
   }
+  for (PassSpec& ps : S.passes) ps.args.xcd_remap = ov.xcd;
   *out = S;
   return FFT_OK;
 }
@@ -294,7 +413,9 @@ int build_schedule(const int64_t* n, int64_t batch, int dims, int dtype, const c
 // plan object
 // ---------------------------------------------------------------------------
 struct fft_plan_s {
-  int kind = 0;  // 0 = strided passes, 1 = batched uneven (many)
+  int kind = 0;  // 0 = strided passes, 1 = batched uneven (many), 2 = per-level method
+  void* lv_buf = nullptr;  // kind 2: ping-pong buffer (also listed in aux)
+  int cus = 0;
   int64_t n[2] = {1, 1};
   int dims = 1, dtype = 0, direction = -1;
   int64_t batch = 1;
@@ -303,6 +424,7 @@ struct fft_plan_s {
   Schedule sched;
   float2* d_tables = nullptr;
   size_t table_bytes = 0;
+  std::vector<void*> aux;  // other plan-owned device buffers (row maps)
   bool gpu_twiddles = false;
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -471,6 +593,11 @@ namespace {
 struct ManyOptions {
   int P = 16, threads = 256, pass2 = 0;  // pass2 0: two passes above the longest one-tile length
   bool given_order = false;
+  // 0: every first-pass tile ahead of every second-pass tile; k > 0: the
+  // second-pass tiles of split transform i follow the first-pass tiles of
+  // split transform i + k, so its intermediate is still in the last-level
+  // cache when it is read back
+  int lag = 0;
 };
 
 int parse_many_schedule(const char* s, ManyOptions* o) {
@@ -500,6 +627,9 @@ int parse_many_schedule(const char* s, ManyOptions* o) {
     else if (key == "pass2") {
       if (v < 1) return FFT_ERR_INVALID_ARGUMENT;
       o->pass2 = (int)v;
+    } else if (key == "lag") {
+      if (v < 0 || v > (1 << 24)) return FFT_ERR_INVALID_ARGUMENT;
+      o->lag = (int)v;
     }
     else return FFT_ERR_INVALID_ARGUMENT;
   }
@@ -547,7 +677,7 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
   if (rc) return rc;
   fft_plan_s* p = new (std::nothrow) fft_plan_s();
   if (!p) return FFT_ERR_NO_MEMORY;
-  p->kind = 0;
+  p->kind = S.levels ? 2 : 0;
   p->dims = dims;
   p->n[0] = n[0];
   p->n[1] = dims == 2 ? n[1] : 1;
@@ -564,23 +694,24 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
   // twiddle tables
   TableBuild tb;
   std::vector<int64_t> stage_off(S.passes.size(), 0);
-  int64_t lo_off = -1, hi_off = -1, step_off = -1;
+  std::vector<int64_t> lo_off(S.passes.size(), -1), hi_off(S.passes.size(), -1),
+      step_off(S.passes.size(), -1);
   for (size_t i = 0; i < S.passes.size(); ++i) {
     const PassSpec& ps = S.passes[i];
     if (!ps.v) continue;
     stage_off[i] = tb.add_stage_table(ps.v->L, ps.v->P);
-    if (ps.v->role == ROLE_SPLIT_A) {
-      // W_N^{n2*k1} with k1 = t + q*T: a per-lane base W_N^{n2*t} (lo/hi
-      // factors) times a per-line step W_N^{n2*q*T} (table [N2][P])
-      const int64_t N = n[0];
+    if (ps.tw_N) {
+      // W_M^{row*k} with k = t + q*T: a per-lane base W_M^{row*t} (lo/hi
+      // factors) times a per-row step W_M^{row*q*T} (table [rows][P])
+      const int64_t M = ps.tw_N;
       const int sh = ps.args.tw_shift;
-      const int64_t N2 = S.split[1];
       const int64_t T = ps.v->L / ps.v->P;
-      lo_off = tb.add((int64_t)1 << sh, 0, N, 1);
-      hi_off = tb.add(N >> sh, 0, N, (int64_t)1 << sh);
-      step_off = tb.add(N2 * ps.v->P, ps.v->P, N, T);
+      lo_off[i] = tb.add((int64_t)1 << sh, 0, M, 1);
+      hi_off[i] = tb.add(M >> sh, 0, M, (int64_t)1 << sh);
+      step_off[i] = tb.add(ps.tw_rows * ps.v->P, ps.v->P, M, T);
     }
   }
+  if (S.levels) tb.add(n[0] / 2, 0, n[0], 1);  // W_N^m, m < N/2
   const bool on_gpu = dims == 1 && ilog2_64(n[0]) >= kGpuTwiddleMinLog2;
   rc = upload_tables(p, tb, on_gpu);
   if (rc) {
@@ -593,6 +724,16 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
     fft_destroy(p);
     return hip_fail(e);
   }
+  p->cus = cus;
+  if (S.levels) {
+    e = hipMalloc(&p->lv_buf, (size_t)S.points * esize(dtype));
+    if (e != hipSuccess) {
+      p->lv_buf = nullptr;
+      fft_destroy(p);
+      return e == hipErrorOutOfMemory ? FFT_ERR_NO_MEMORY : hip_fail(e);
+    }
+    p->aux.push_back(p->lv_buf);
+  }
   for (size_t i = 0; i < p->sched.passes.size(); ++i) {
     PassSpec& ps = p->sched.passes[i];
     if (!ps.v) continue;
@@ -602,10 +743,23 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
       ps.args.grid = (int32_t)std::min<int64_t>(ps.args.total_tiles, (int64_t)per_cu * cus);
     }
     ps.args.tw = p->d_tables + stage_off[i];
-    if (ps.v->role == ROLE_SPLIT_A) {
-      ps.args.tw_lo = p->d_tables + lo_off;
-      ps.args.tw_hi = p->d_tables + hi_off;
-      ps.args.tw_step = p->d_tables + step_off;
+    if (ps.tw_N) {
+      ps.args.tw_lo = p->d_tables + lo_off[i];
+      ps.args.tw_hi = p->d_tables + hi_off[i];
+      ps.args.tw_step = p->d_tables + step_off[i];
+    }
+    if (!ps.line_map.empty()) {
+      const size_t bytes = ps.line_map.size() * sizeof(int32_t);
+      int32_t* d = nullptr;
+      e = hipMalloc((void**)&d, bytes);
+      if (e == hipSuccess) e = hipMemcpy(d, ps.line_map.data(), bytes, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        if (d) hipFree(d);
+        fft_destroy(p);
+        return e == hipErrorOutOfMemory ? FFT_ERR_NO_MEMORY : hip_fail(e);
+      }
+      p->aux.push_back(d);
+      ps.args.line_map = d;
     }
   }
   *out = p;
@@ -675,6 +829,27 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
   const bool overlap = ib < ob + bytes && ob < ib + bytes;
   const bool same = in == out;
   if (overlap && !same) return FFT_ERR_INPLACE;
+  if (p->kind == 2) {
+    LevelsArgs la;
+    la.in = in;
+    la.out = out;
+    la.buf = p->lv_buf;
+    la.batch = p->batch;
+    la.lgN = ilog2_64(p->n[0]);
+    la.dtype = p->dtype;
+    la.tw = p->d_tables;
+    la.scale = (float)p->scale;
+    la.user_scale = p->scale_user;
+    la.inverse = p->direction > 0;
+    la.cus = p->cus;
+    hipEvent_t* slot = prof_slot(p);
+    if (slot) hipEventRecord(slot[0], s);
+    hipError_t e = launch_levels(la, s);
+    if (slot) hipEventRecord(slot[1], s);
+    if (e != hipSuccess) return hip_fail(e);
+    prof_commit(p);
+    return FFT_OK;
+  }
   void* ws = nullptr;
   if (same && S.passes.size() > 1 && S.inplace_needs_ws) {
     if (!p->ws) return FFT_ERR_INPLACE;
@@ -733,6 +908,17 @@ int fft_plan_info(fft_plan_t p, fft_plan_info_t* info) {
     return FFT_OK;
   }
   const Schedule& S = p->sched;
+  if (p->kind == 2) {
+    // the whole sequence of log2 N level launches is reported as one entry
+    const double lg = (double)ilog2_64(p->n[0]);
+    info->passes = 1;
+    snprintf(info->pass_variant[0], 32, "%s", "levels_radix2");
+    info->points = S.points;
+    info->flops = 5.0 * (double)p->n[0] * lg * (double)p->batch;
+    info->bytes_min = 2.0 * es * (double)S.points;
+    info->bytes_pass[0] = lg * 2.0 * es * (double)S.points;
+    return FFT_OK;
+  }
   info->passes = (int)S.passes.size();
   info->split[0] = S.split[0];
   info->split[1] = S.split[1];
@@ -751,6 +937,7 @@ int fft_destroy(fft_plan_t p) {
   if (!p) return FFT_OK;
   for (hipEvent_t e : p->ev) hipEventDestroy(e);
   if (p->d_tables) hipFree(p->d_tables);
+  for (void* b : p->aux) hipFree(b);
   if (p->ws_owned && p->ws) hipFree(p->ws);
   many_free(p->many);
   delete p;
@@ -797,10 +984,12 @@ int fft_describe(const int64_t* n, int64_t batch, int dims, int dtype, const cha
   Schedule S;
   int rc = build_schedule(n, batch, dims, dtype, schedule, &S);
   if (rc) return rc;
-  if (passes) *passes = (int)S.passes.size();
+  if (passes) *passes = S.levels ? 1 : (int)S.passes.size();
   if (names)
     for (size_t i = 0; i < 4; ++i)
-      snprintf(names[i], 32, "%s", i < S.passes.size() ? (S.passes[i].v ? S.passes[i].v->name : "copy_scale") : "");
+      snprintf(names[i], 32, "%s",
+               S.levels ? (i == 0 ? "levels_radix2" : "")
+                        : i < S.passes.size() ? (S.passes[i].v ? S.passes[i].v->name : "copy_scale") : "");
   if (split) {
     split[0] = S.split[0];
     split[1] = S.split[1];
@@ -816,7 +1005,7 @@ int fft_profile_enable(fft_plan_t p, int slots) {
   p->prof_slots = 0;
   p->prof_next = 0;
   p->prof_pending = 0;
-  p->prof_npass = p->kind == 1 ? 1 : p->sched.passes.size();
+  p->prof_npass = p->kind != 0 ? 1 : p->sched.passes.size();
   p->prof_ms.assign(p->prof_npass, 0.0);
   p->prof_n.assign(p->prof_npass, 0);
   if (!slots) return FFT_OK;
@@ -929,14 +1118,29 @@ int build_many(const int64_t* sizes, int64_t count, int dtype, int direction, co
   if (!opt.given_order)
     std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) { return lgs[a] > lgs[b]; });
 
-  // items: all first-pass tiles, then one-pass tiles, then second-pass tiles
+  // items: first-pass tiles, one-pass tiles, second-pass tiles.  Every
+  // first-pass tile of a transform precedes its second-pass tiles, so the
+  // tiles a waiting second-pass tile depends on have all been taken by
+  // running workgroups, which never wait themselves.
   std::vector<ManyItem>& items = mb->items;
   std::vector<int32_t>& order = mb->order;
-  for (int32_t id : ids) {
+  std::vector<int32_t> split_ids;
+  for (int32_t id : ids)
+    if (xf[id].nA) split_ids.push_back(id);
+  auto push_b = [&](int32_t id) {
     const ManyXform& x = xf[id];
-    if (x.nA == 0) continue;
+    const int lg2 = x.lg - x.lg1;
+    const int64_t N1 = (int64_t)1 << x.lg1;
+    const int wb = tile_lines(lg2, opt.P, opt.threads);
+    const int nb = (int)((N1 + wb - 1) / wb);
+    for (int t = 0; t < nb; ++t) items.push_back({MANY_B, lg2, id, t});
+  };
+  size_t b_next = 0;  // split transforms whose second-pass tiles are queued
+  for (size_t i = 0; i < split_ids.size(); ++i) {
+    const ManyXform& x = xf[split_ids[i]];
     mb->has_split = true;
-    for (int t = 0; t < x.nA; ++t) items.push_back({MANY_A, x.lg1, id, t});
+    for (int t = 0; t < x.nA; ++t) items.push_back({MANY_A, x.lg1, split_ids[i], t});
+    if (opt.lag > 0 && i >= (size_t)opt.lag) push_b(split_ids[b_next++]);
   }
   {
     // one-pass transforms grouped by length, W lines per tile
@@ -964,15 +1168,7 @@ int build_many(const int64_t* sizes, int64_t count, int dtype, int direction, co
       }
     }
   }
-  for (int32_t id : ids) {
-    const ManyXform& x = xf[id];
-    if (x.nA == 0) continue;
-    const int lg2 = x.lg - x.lg1;
-    const int64_t N1 = (int64_t)1 << x.lg1;
-    const int wb = tile_lines(lg2, opt.P, opt.threads);
-    const int nb = (int)((N1 + wb - 1) / wb);
-    for (int t = 0; t < nb; ++t) items.push_back({MANY_B, lg2, id, t});
-  }
+  while (b_next < split_ids.size()) push_b(split_ids[b_next++]);
   if (items.size() > (size_t)INT32_MAX) return FFT_ERR_UNSUPPORTED_SIZE;
   return FFT_OK;
 }

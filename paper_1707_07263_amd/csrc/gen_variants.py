@@ -10,7 +10,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LDS_MAX = 160 * 1024
 DT = {"c64": "float2", "f16": "__half2", "bf16": "c16bf"}
-ROLE = {"r": "ROLE_ROW", "a": "ROLE_SPLIT_A", "c": "ROLE_COL"}
+ROLE = {"r": "ROLE_ROW", "a": "ROLE_SPLIT_A", "c": "ROLE_COL", "t": "ROLE_COL_TW"}
 
 
 def lds_bytes(L, W, ex=0):
@@ -78,6 +78,21 @@ def col_set():
     return strided_set(1, 14, "c")
 
 
+def coltw_set():
+    """Columns with a twiddle (first column sub-pass of the three-pass 2-D
+    plan): lengths 2..128, wide strips."""
+    out = []
+    for lg in range(1, 8):
+        L = 1 << lg
+        for P in (8, 16):
+            if P > L and P != 8:
+                continue
+            for W in (8, 16, 32, 64):
+                if ok(L, P, W, 0, min_threads=64 if L >= 64 else 1):
+                    out.append((L, P, W, 0))
+    return out
+
+
 def c16_set():
     # one variant per (role, L) for the 16-bit storage types
     out = []
@@ -101,7 +116,19 @@ def c16_set():
         while not ok(L, 16, W, min_threads=1) and W > 1:
             W //= 2
         out.append(("c", L, 16, W, 0))
-    return out
+    for lg in range(1, 8):
+        out.append(("t", 1 << lg, 16, 16, 0))
+    # three-pass 2-D: wide column tiles for the two short column passes, and
+    # rows paired with their transposes (an even number of rows per tile)
+    for lg in range(4, 8):
+        L = 1 << lg
+        for role in ("t", "c"):
+            if ok(L, 16, 64):
+                out.append((role, L, 16, 64, 0))
+    for lg in range(11, 13):
+        if ok(1 << lg, 16, 2):
+            out.append(("r", 1 << lg, 16, 2, 0))
+    return list(dict.fromkeys(out))
 
 
 def name(role, L, P, W, ex, dt, persist=0):
@@ -173,7 +200,8 @@ def main():
     for dt in ("f16", "bf16"):
         items += [v + (dt,) for v in c16_set()]
     emit("variants_c16.hip", "add_variants_c16", items)
-    emit("variants_c64_pipe.hip", "add_variants_c64_pipe", [v + ("c64", 1) for v in pipe_set()])
+    emit("variants_c64_pipe.hip", "add_variants_c64_pipe",
+         [v + ("c64", 1) for v in pipe_set()] + [("t",) + v + ("c64",) for v in coltw_set()])
 
 
 if __name__ == "__main__":

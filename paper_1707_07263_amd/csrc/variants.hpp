@@ -10,7 +10,7 @@
 
 namespace mfft {
 
-enum Role { ROLE_ROW = 0, ROLE_SPLIT_A = 1, ROLE_COL = 2 };
+enum Role { ROLE_ROW = 0, ROLE_SPLIT_A = 1, ROLE_COL = 2, ROLE_COL_TW = 3 };
 enum Dtype { DT_C64 = 0, DT_C16F = 1, DT_C16BF = 2 };
 
 using LaunchFn = hipError_t (*)(const PassArgs&, hipStream_t);
@@ -59,8 +59,8 @@ template <> struct DtOf<c16bf> { static constexpr int v = DT_C16BF; };
 template <int ROLE, int L, int P, int W, int EX, typename TS, int PERSIST = 0>
 Variant make_variant(const char* name) {
   constexpr int LOADM = ROLE == ROLE_ROW ? 0 : 1;
-  constexpr int STOREM = ROLE == ROLE_COL ? 1 : 0;
-  constexpr bool TWID = ROLE == ROLE_SPLIT_A;
+  constexpr int STOREM = (ROLE == ROLE_COL || ROLE == ROLE_COL_TW) ? 1 : 0;
+  constexpr bool TWID = ROLE == ROLE_SPLIT_A || ROLE == ROLE_COL_TW;
   Variant v;
   v.name = name;
   v.L = L;

@@ -34,6 +34,49 @@ void add_variants_c64_pipe(void (*add)(const Variant&)) {
   add(make_variant<ROLE_ROW, 4096, 16, 1, 0, float2, 1>("r4096p16w1q_c64"));
   add(make_variant<ROLE_ROW, 4096, 16, 2, 0, float2, 1>("r4096p16w2q_c64"));
   add(make_variant<ROLE_ROW, 4096, 16, 4, 1, float2, 1>("r4096p16w4qx_c64"));
+  add(make_variant<ROLE_COL_TW, 2, 8, 8, 0, float2, 0>("t2p2w8_c64"));
+  add(make_variant<ROLE_COL_TW, 2, 8, 16, 0, float2, 0>("t2p2w16_c64"));
+  add(make_variant<ROLE_COL_TW, 2, 8, 32, 0, float2, 0>("t2p2w32_c64"));
+  add(make_variant<ROLE_COL_TW, 2, 8, 64, 0, float2, 0>("t2p2w64_c64"));
+  add(make_variant<ROLE_COL_TW, 4, 8, 8, 0, float2, 0>("t4p4w8_c64"));
+  add(make_variant<ROLE_COL_TW, 4, 8, 16, 0, float2, 0>("t4p4w16_c64"));
+  add(make_variant<ROLE_COL_TW, 4, 8, 32, 0, float2, 0>("t4p4w32_c64"));
+  add(make_variant<ROLE_COL_TW, 4, 8, 64, 0, float2, 0>("t4p4w64_c64"));
+  add(make_variant<ROLE_COL_TW, 8, 8, 8, 0, float2, 0>("t8p8w8_c64"));
+  add(make_variant<ROLE_COL_TW, 8, 8, 16, 0, float2, 0>("t8p8w16_c64"));
+  add(make_variant<ROLE_COL_TW, 8, 8, 32, 0, float2, 0>("t8p8w32_c64"));
+  add(make_variant<ROLE_COL_TW, 8, 8, 64, 0, float2, 0>("t8p8w64_c64"));
+  add(make_variant<ROLE_COL_TW, 16, 8, 8, 0, float2, 0>("t16p8w8_c64"));
+  add(make_variant<ROLE_COL_TW, 16, 8, 16, 0, float2, 0>("t16p8w16_c64"));
+  add(make_variant<ROLE_COL_TW, 16, 8, 32, 0, float2, 0>("t16p8w32_c64"));
+  add(make_variant<ROLE_COL_TW, 16, 8, 64, 0, float2, 0>("t16p8w64_c64"));
+  add(make_variant<ROLE_COL_TW, 16, 16, 8, 0, float2, 0>("t16p16w8_c64"));
+  add(make_variant<ROLE_COL_TW, 16, 16, 16, 0, float2, 0>("t16p16w16_c64"));
+  add(make_variant<ROLE_COL_TW, 16, 16, 32, 0, float2, 0>("t16p16w32_c64"));
+  add(make_variant<ROLE_COL_TW, 16, 16, 64, 0, float2, 0>("t16p16w64_c64"));
+  add(make_variant<ROLE_COL_TW, 32, 8, 8, 0, float2, 0>("t32p8w8_c64"));
+  add(make_variant<ROLE_COL_TW, 32, 8, 16, 0, float2, 0>("t32p8w16_c64"));
+  add(make_variant<ROLE_COL_TW, 32, 8, 32, 0, float2, 0>("t32p8w32_c64"));
+  add(make_variant<ROLE_COL_TW, 32, 8, 64, 0, float2, 0>("t32p8w64_c64"));
+  add(make_variant<ROLE_COL_TW, 32, 16, 8, 0, float2, 0>("t32p16w8_c64"));
+  add(make_variant<ROLE_COL_TW, 32, 16, 16, 0, float2, 0>("t32p16w16_c64"));
+  add(make_variant<ROLE_COL_TW, 32, 16, 32, 0, float2, 0>("t32p16w32_c64"));
+  add(make_variant<ROLE_COL_TW, 32, 16, 64, 0, float2, 0>("t32p16w64_c64"));
+  add(make_variant<ROLE_COL_TW, 64, 8, 8, 0, float2, 0>("t64p8w8_c64"));
+  add(make_variant<ROLE_COL_TW, 64, 8, 16, 0, float2, 0>("t64p8w16_c64"));
+  add(make_variant<ROLE_COL_TW, 64, 8, 32, 0, float2, 0>("t64p8w32_c64"));
+  add(make_variant<ROLE_COL_TW, 64, 8, 64, 0, float2, 0>("t64p8w64_c64"));
+  add(make_variant<ROLE_COL_TW, 64, 16, 16, 0, float2, 0>("t64p16w16_c64"));
+  add(make_variant<ROLE_COL_TW, 64, 16, 32, 0, float2, 0>("t64p16w32_c64"));
+  add(make_variant<ROLE_COL_TW, 64, 16, 64, 0, float2, 0>("t64p16w64_c64"));
+  add(make_variant<ROLE_COL_TW, 128, 8, 8, 0, float2, 0>("t128p8w8_c64"));
+  add(make_variant<ROLE_COL_TW, 128, 8, 16, 0, float2, 0>("t128p8w16_c64"));
+  add(make_variant<ROLE_COL_TW, 128, 8, 32, 0, float2, 0>("t128p8w32_c64"));
+  add(make_variant<ROLE_COL_TW, 128, 8, 64, 0, float2, 0>("t128p8w64_c64"));
+  add(make_variant<ROLE_COL_TW, 128, 16, 8, 0, float2, 0>("t128p16w8_c64"));
+  add(make_variant<ROLE_COL_TW, 128, 16, 16, 0, float2, 0>("t128p16w16_c64"));
+  add(make_variant<ROLE_COL_TW, 128, 16, 32, 0, float2, 0>("t128p16w32_c64"));
+  add(make_variant<ROLE_COL_TW, 128, 16, 64, 0, float2, 0>("t128p16w64_c64"));
 }
 
 }  // namespace mfft

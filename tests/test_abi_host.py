@@ -50,10 +50,10 @@ def test_variant_registry(lib):
         d = capi.fft_variant_describe(i)
         assert name not in seen
         seen.add(name)
-        m = re.match(r"([rac])(\d+)p(\d+)w(\d+)(q?)(x?)_(c64|f16|bf16)$", name)
+        m = re.match(r"([ract])(\d+)p(\d+)w(\d+)(q?)(x?)_(c64|f16|bf16)$", name)
         assert m, name
         assert int(m.group(2)) == d["L"] and int(m.group(3)) == d["P"] and int(m.group(4)) == d["W"]
-        assert {"r": 0, "a": 1, "c": 2}[m.group(1)] == d["role"]
+        assert {"r": 0, "a": 1, "c": 2, "t": 3}[m.group(1)] == d["role"]
         assert {"c64": 0, "f16": 1, "bf16": 2}[m.group(7)] == d["dtype"]
         assert d["threads"] == d["W"] * d["L"] // d["P"] and d["threads"] <= 1024
     assert capi.fft_variant_name(n) is None
@@ -65,7 +65,8 @@ def test_variant_registry(lib):
     ([1 << 15], 1, 4, 2, [256, 128]),          # first length that needs the split
     ([1 << 20], 1, 16, 2, [1024, 1024]),
     ([1 << 24], 1, 1, 2, [4096, 4096]),
-    ([4096, 4096], 2, 1, 2, [0, 0]),           # rows, then columns
+    ([4096, 4096], 2, 1, 3, [0, 0]),           # rows, then columns as two sub-passes
+    ([2048, 4096], 2, 1, 2, [0, 0]),           # rows, then columns
     ([1, 64], 2, 3, 1, [0, 0]),                # a length-1 axis needs no pass
     ([64, 1], 2, 3, 1, [0, 0]),
     ([1], 1, 5, 1, [0, 0]),
@@ -153,3 +154,33 @@ def test_package_imports_without_gpu():
     from paper_1707_07263_amd import api  # noqa: F401
     assert callable(pkg.fft) and callable(pkg.fft2) and callable(pkg.fft_many)
     assert pkg.FFTFunction is api.FFTFunction
+
+
+def test_describe_three_pass_2d(lib):
+    d = capi.fft_describe([4096, 4096], 1, 2, capi.FFT_C64)
+    assert d["passes"] == 3
+    assert d["names"][0].startswith("t64p") and d["names"][1].startswith("c64p")
+    assert d["names"][2].startswith("r4096p")
+    assert capi.fft_describe([4096, 4096], 1, 2, capi.FFT_C64, "col3=0")["passes"] == 2
+    d = capi.fft_describe([1024, 64], 3, 2, capi.FFT_C64, "col3=1")
+    assert d["passes"] == 3 and d["names"][0].startswith("t32p")
+    # rows not a power of four, or a single column: refused when asked for,
+    # and the automatic choice falls back to two passes
+    for shape in ([2048, 64], [4096, 1]):
+        with pytest.raises(capi.FFTError):
+            capi.fft_describe(shape, 1, 2, capi.FFT_C64, "col3=1")
+        assert capi.fft_describe(shape, 1, 2, capi.FFT_C64)["passes"] <= 2
+    # a row variant with an odd number of rows per tile cannot pair rows
+    assert capi.fft_describe([4096, 4096], 1, 2, capi.FFT_C64, "row=r4096p16w1q_c64")["passes"] == 2
+
+
+def test_describe_levels_method(lib):
+    d = capi.fft_describe([1 << 20], 16, 1, capi.FFT_C64, "method=levels")
+    assert d["passes"] == 1 and d["names"][0] == "levels_radix2"
+    assert capi.fft_describe([1 << 20], 16, 1, capi.FFT_C64, "method=lds")["passes"] == 2
+    # a length-1 transform is a copy under either method
+    assert capi.fft_describe([1], 3, 1, capi.FFT_C64, "method=levels")["names"][0] == "copy_scale"
+    for bad, dims, n in (("method=levels", 2, [64, 64]), ("method=radix2", 1, [64])):
+        with pytest.raises(capi.FFTError) as ei:
+            capi.fft_describe(n, 1, dims, capi.FFT_C64, bad)
+        assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT

@@ -104,7 +104,7 @@ def test_uneven_512_16bit(dev, dt):
 
 
 @pytest.mark.parametrize("schedule", [None, "p=8", "pass2=10", "pass2=13;order=given",
-                                      "threads=512", "pass2=1"])
+                                      "threads=512", "pass2=1", "lag=1", "lag=3;pass2=9"])
 def test_many_schedules_and_small_sizes(dev, schedule):
     # every length 2^0..2^16 twice, shuffled, under each compiled schedule
     g = workloads.rng(77)
@@ -117,6 +117,18 @@ def test_many_schedules_and_small_sizes(dev, schedule):
     errs = per_transform_errors(got, ref, sizes)
     tol = 1e-6 * np.maximum(1.0, np.log2(sizes.astype(np.float64)))
     assert np.all(errs <= tol), (schedule, float((errs / tol).max()))
+
+
+@pytest.mark.parametrize("schedule", ["lag=0", "lag=2", "threads=512;lag=1"])
+def test_many_16x2p20_lagged_queue(dev, schedule):
+    # sixteen 2^20-point transforms in one launch, second passes interleaved
+    # with later first passes
+    sizes = np.array([1 << 20] * 16, dtype=np.int64)
+    x = workloads.normal_batch(1 << 20, 16, seed=88).astype(np.complex64)
+    got = run_many_c64(x.reshape(-1), sizes, dev, schedule=schedule)
+    ref = oracle.fft(x).reshape(-1)
+    errs = per_transform_errors(got, ref, sizes)
+    assert errs.max() <= 1e-6 * 20, (schedule, float(errs.max()))
 
 
 def test_many_inverse_scale_and_repeat(dev):

@@ -21,7 +21,7 @@ def dev():
 
 
 @pytest.mark.parametrize("tname", ["float16", "bfloat16"])
-@pytest.mark.parametrize("shape", [(256,), (4096,), (1 << 14,), (1 << 16,), (1 << 20,), (64, 512), (1024, 1024)])
+@pytest.mark.parametrize("shape", [(256,), (4096,), (1 << 14,), (1 << 16,), (1 << 20,), (64, 512), (1024, 1024), (4096, 64)])
 def test_16bit_storage(dev, tname, shape):
     tdt = getattr(torch, tname)
     n = int(np.prod(shape))
@@ -42,6 +42,25 @@ def test_16bit_storage(dev, tname, shape):
     ref_z = (oracle.fft2(from_gpu_16(y), inverse=True) if len(shape) == 2
              else oracle.ifft(from_gpu_16(y))).reshape(b, -1)
     assert rel_l2_rows(from_gpu_16(z).reshape(b, -1), ref_z, n).max() <= TOL16[tname]
+
+
+@pytest.mark.parametrize("tname", ["float16", "bfloat16"])
+@pytest.mark.parametrize("shape", [(64, 512), (256, 32), (16, 16)])
+def test_16bit_three_pass_2d(dev, tname, shape):
+    # columns as two sub-passes, forced by the schedule
+    tdt = getattr(torch, tname)
+    try:
+        capi.fft_describe(list(shape), 3, 2, capi.FFT_C16F if tname == "float16" else capi.FFT_C16BF,
+                          "col3=1")
+    except capi.FFTError:
+        pytest.skip("no three-pass schedule for this shape")
+    n = int(np.prod(shape))
+    x = workloads.normal_batch(n, 3, seed=7 + n).reshape((3,) + shape)
+    xq = quantised(x, tdt)
+    y = api.fft2(to_gpu_16(x, dev, tdt), schedule="col3=1")
+    torch.cuda.synchronize()
+    err = rel_l2_rows(from_gpu_16(y).reshape(3, -1), oracle.fft2(xq).reshape(3, -1), n)
+    assert err.max() <= TOL16[tname], float(err.max())
 
 
 def test_wrappers_match_capi(dev):
@@ -98,3 +117,18 @@ def test_graph_capture_replay_strided(dev, shape):
         del g
     finally:
         capi.fft_destroy(h)
+
+
+@pytest.mark.parametrize("tname", ["float16", "bfloat16"])
+def test_16bit_4096x4096_image(dev, tname):
+    # the image workload in 16-bit storage (columns as two sub-passes)
+    tdt = getattr(torch, tname)
+    z = workloads.speckle_image(4096, 4096, seed=2)
+    d = capi.fft_describe([4096, 4096], 1, 2, capi.FFT_C16F if tname == "float16" else capi.FFT_C16BF)
+    print(f"{tname} 4096x4096 passes: {d['names'][:d['passes']]}")
+    y = api.fft2(to_gpu_16(z[None], dev, tdt))
+    torch.cuda.synchronize()
+    err = rel_l2_rows(from_gpu_16(y).reshape(1, -1), oracle.fft2(quantised(z[None], tdt)).reshape(1, -1),
+                      4096 * 4096)
+    print(f"{tname} 4096x4096 image rel-L2 {err.max():.3e}")
+    assert err.max() <= TOL16[tname], float(err.max())

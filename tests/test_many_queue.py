@@ -82,7 +82,8 @@ def test_uneven_512_queue():
 
 
 @pytest.mark.parametrize("schedule", [None, "p=8", "pass2=10", "pass2=13;order=given",
-                                      "threads=512", "pass2=1", "pass2=2;order=given"])
+                                      "threads=512", "pass2=1", "pass2=2;order=given",
+                                      "lag=1", "lag=3;pass2=9", "lag=100"])
 def test_queue_all_lengths(schedule):
     g = np.random.default_rng(5)
     sizes = np.array([1 << e for e in list(range(0, 17)) * 2])
@@ -102,7 +103,27 @@ def test_queue_errors():
         with pytest.raises(capi.FFTError) as ei:
             capi.fft_describe_many(sizes)
         assert ei.value.status == code
-    for bad in ("p=7", "threads=100", "pass2=0", "pass2=14", "order=random", "x=1"):
+    for bad in ("p=7", "threads=100", "pass2=0", "pass2=14", "order=random", "x=1", "lag=-1"):
         with pytest.raises(capi.FFTError) as ei:
             capi.fft_describe_many([256], schedule=bad)
         assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT, bad
+
+
+def test_queue_lag_interleaves():
+    # with lag k the second-pass tiles of split transform i come right after
+    # the first-pass tiles of transform i + k
+    sizes = [1 << 20] * 6
+    items, ft = check_queue(sizes, "lag=2")
+    kinds = [(int(k), int(a)) for k, _, a, _ in items]
+    runs = []
+    for k, a in kinds:
+        if not runs or runs[-1] != (k, a):
+            runs.append((k, a))
+    assert runs == [(FIRST, 0), (FIRST, 1), (FIRST, 2), (SECOND, 0), (FIRST, 3), (SECOND, 1),
+                    (FIRST, 4), (SECOND, 2), (FIRST, 5), (SECOND, 3), (SECOND, 4), (SECOND, 5)]
+    for workers in (1, 2, 300):
+        simulate(items, ft, workers, np.random.default_rng(workers))
+    # lag 0 keeps every first-pass tile first
+    items0, _ = check_queue(sizes)
+    first = [i for i, it in enumerate(items0) if it[0] == FIRST]
+    assert first == list(range(len(first)))
