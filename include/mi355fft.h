@@ -89,7 +89,9 @@ int fft_plan(const int64_t *n, int64_t batch, int dims, int dtype, int direction
  *   item     := 'split=' N1            (1-D two-pass: first-pass length)
  *             | 'a=' variant | 'b=' variant | 'row=' variant | 'col=' variant
  *             | 'single=' variant
- *             | 'xcd=' 0|1            (1: consecutive tiles run on one XCD)
+ *             | 'xcd=' digits         (one '0'/'1' for every pass, or one digit
+ *                                       per pass, first pass first; 1: consecutive
+ *                                       tiles run on one XCD, sharing its L2)
  *             | 'col3=' 0|1           (2-D: columns as two sub-passes of sqrt(rows)
  *                                       points; rows a power of 4, at least 2 columns)
  *             | 'colt=' variant       (the first of those sub-passes)

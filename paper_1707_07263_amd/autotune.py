@@ -197,8 +197,30 @@ def tune_plan(shape, batch, dtype=capi.FFT_C64, reps=10, verbose=False):
     else:
         return "", base[1]
 
+    def sched_of(d):
+        return ";".join(f"{k}={v}" for k, v in d.items())
+
+    def xcd_search(cur):
+        # per-pass XCD remap: every mask over the plan's passes
+        base = run(sched_of(cur))
+        if base is None:
+            return cur
+        npass = base[2]["passes"]
+        best = (base[0], cur.get("xcd"))
+        for m in range(1 << npass):
+            mask = "".join("1" if (m >> i) & 1 else "0" for i in range(npass))
+            trial = dict(cur)
+            trial["xcd"] = mask
+            r = run(sched_of(trial))
+            if r is not None and r[0] < best[0]:
+                best = (r[0], mask)
+        out = dict(cur)
+        if best[1] is not None:
+            out["xcd"] = best[1]
+        return out
+
     def descend(prefix, keys, start):
-        cur = dict(start)
+        cur = xcd_search(dict(start))
         for _ in range(2):
             for key, role, L in keys:
                 best = None
@@ -211,7 +233,7 @@ def tune_plan(shape, batch, dtype=capi.FFT_C64, reps=10, verbose=False):
                         best = (r[0], nm)
                 if best is not None:
                     cur[key] = best[1]
-        return cur
+        return xcd_search(cur)
 
     if splits == [None]:
         for st in starts:

@@ -120,7 +120,9 @@ struct Schedule {
 
 struct Overrides {
   int64_t split = 0;
-  int xcd = 0;    // 1: map consecutive tiles to one XCD
+  // per pass, 1: consecutive tiles run on one XCD.  One digit applies to
+  // every pass; otherwise one digit per pass, first pass first.
+  std::string xcd = "0";
   int col3 = -1;  // 2-D columns in two sub-passes: 1 yes, 0 no, -1 automatic
   bool levels = false;  // method=levels: the per-level global-memory method
   std::string a, b, row, col, single, colt;
@@ -145,8 +147,9 @@ int parse_schedule(const char* s, Overrides* o) {
       if (!e || *e || v < 1) return FFT_ERR_INVALID_ARGUMENT;
       o->split = v;
     } else if (key == "xcd") {
-      if (val != "0" && val != "1") return FFT_ERR_INVALID_ARGUMENT;
-      o->xcd = val == "1";
+      if (val.empty() || val.size() > 4 || val.find_first_not_of("01") != std::string::npos)
+        return FFT_ERR_INVALID_ARGUMENT;
+      o->xcd = val;
     } else if (key == "col3") {
       if (val != "0" && val != "1") return FFT_ERR_INVALID_ARGUMENT;
       o->col3 = val == "1";
@@ -253,17 +256,11 @@ int build_three_pass_2d(int64_t R, int64_t C, int64_t batch, int dtype, const Ov
   S.passes.push_back(rw);
   S.passes.front().first = true;
   S.passes.back().last = true;
-  for (PassSpec& ps : S.passes) ps.args.xcd_remap = ov.xcd;
   return FFT_OK;
-
 }
 
-int build_schedule(const int64_t* n, int64_t batch, int dims, int dtype, const char* sched,
-                   Schedule* out) {
-  if (!n || batch < 1 || (dims != 1 && dims != 2)) return FFT_ERR_INVALID_ARGUMENT;
-  if (dtype != FFT_C64 && dtype != FFT_C16F && dtype != FFT_C16BF) return FFT_ERR_INVALID_ARGUMENT;
-  Overrides ov;
-  if (parse_schedule(sched, &ov) != FFT_OK) return FFT_ERR_INVALID_ARGUMENT;
+int build_schedule_inner(const int64_t* n, int64_t batch, int dims, int dtype, const Overrides& ov,
+                         Schedule* out) {
   Schedule S;
   if (dims == 1) {
     const int64_t N = n[0];
@@ -402,7 +399,30 @@ int build_schedule(const int64_t* n, int64_t batch, int dims, int dtype, const c
     S.passes.front().first = true;
     S.passes.back().last = true;
   }
-  for (PassSpec& ps : S.passes) ps.args.xcd_remap = ov.xcd;
+  *out = S;
+  return FFT_OK;
+}
+
+int apply_xcd(const std::string& mask, Schedule* S) {
+  if (S->levels) return mask == "0" || mask == "1" ? FFT_OK : FFT_ERR_INVALID_ARGUMENT;
+  const size_t n = S->passes.size();
+  if (mask.size() != 1 && mask.size() != n) return FFT_ERR_INVALID_ARGUMENT;
+  for (size_t i = 0; i < n; ++i)
+    S->passes[i].args.xcd_remap = (mask.size() == 1 ? mask[0] : mask[i]) == '1';
+  return FFT_OK;
+}
+
+int build_schedule(const int64_t* n, int64_t batch, int dims, int dtype, const char* sched,
+                   Schedule* out) {
+  if (!n || batch < 1 || (dims != 1 && dims != 2)) return FFT_ERR_INVALID_ARGUMENT;
+  if (dtype != FFT_C64 && dtype != FFT_C16F && dtype != FFT_C16BF) return FFT_ERR_INVALID_ARGUMENT;
+  Overrides ov;
+  if (parse_schedule(sched, &ov) != FFT_OK) return FFT_ERR_INVALID_ARGUMENT;
+  Schedule S;
+  int rc = build_schedule_inner(n, batch, dims, dtype, ov, &S);
+  if (rc) return rc;
+  rc = apply_xcd(ov.xcd, &S);
+  if (rc) return rc;
   *out = S;
   return FFT_OK;
 }

@@ -55,9 +55,13 @@ def strided_set(lo_lg, hi_lg, role):
         for P in (8, 16, 32):
             if P > L and P != 8:
                 continue
-            if P == 32 and (L < 256 or L > 1024):
+            # 32 points per lane: up to 1024 points, and for the long 2-D
+            # column passes (2048, 4096) with 8-16 columns per tile
+            if P == 32 and (L < 256 or L > (4096 if role == "c" else 1024)):
                 continue
             for W in (1, 2, 4, 8, 16, 32, 64):
+                if P == 32 and L > 1024 and W > 16:
+                    continue
                 if role == "a" and W < 4:
                     continue
                 if P == 32 and W < 8:
@@ -156,12 +160,14 @@ def pipe_set():
         for lg in range(8, 13):
             L = 1 << lg
             for P in (16, 32):
-                if P == 32 and L > 1024:
+                if P == 32 and L > 1024 and role != "c":
                     continue
                 for W in ((1, 2, 4) if role == "r" else (8, 16, 32)):
                     for ex in (0, 1):
+                        # 1024 lanes leave 128 registers per lane: too few for
+                        # a tile in flight plus the next one (they spill)
                         t = threads(L, P, W)
-                        if t < 256 or t > 1024:
+                        if t < 256 or t > 512:
                             continue
                         if role == "a" and W * min(P, L) > t:
                             continue

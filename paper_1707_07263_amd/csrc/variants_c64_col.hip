@@ -77,6 +77,8 @@ void add_variants_c64_col(void (*add)(const Variant&)) {
   add(make_variant<ROLE_COL, 256, 8, 32, 0, float2, 0>("c256p8w32_c64"));
   add(make_variant<ROLE_COL, 256, 8, 32, 1, float2, 0>("c256p8w32x_c64"));
   add(make_variant<ROLE_COL, 256, 16, 4, 0, float2, 0>("c256p16w4_c64"));
+  add(make_variant<ROLE_COL, 256, 16, 8, 0, float2, 0>("c256p16w8_c64"));
+  add(make_variant<ROLE_COL, 256, 16, 16, 0, float2, 0>("c256p16w16_c64"));
 }
 
 }  // namespace mfft

@@ -3,8 +3,6 @@
 namespace mfft {
 
 void add_variants_c64_col2(void (*add)(const Variant&)) {
-  add(make_variant<ROLE_COL, 256, 16, 8, 0, float2, 0>("c256p16w8_c64"));
-  add(make_variant<ROLE_COL, 256, 16, 16, 0, float2, 0>("c256p16w16_c64"));
   add(make_variant<ROLE_COL, 256, 16, 32, 0, float2, 0>("c256p16w32_c64"));
   add(make_variant<ROLE_COL, 256, 16, 32, 1, float2, 0>("c256p16w32x_c64"));
   add(make_variant<ROLE_COL, 256, 16, 64, 0, float2, 0>("c256p16w64_c64"));
@@ -61,6 +59,9 @@ void add_variants_c64_col2(void (*add)(const Variant&)) {
   add(make_variant<ROLE_COL, 2048, 16, 4, 1, float2, 0>("c2048p16w4x_c64"));
   add(make_variant<ROLE_COL, 2048, 16, 8, 0, float2, 0>("c2048p16w8_c64"));
   add(make_variant<ROLE_COL, 2048, 16, 8, 1, float2, 0>("c2048p16w8x_c64"));
+  add(make_variant<ROLE_COL, 2048, 32, 8, 0, float2, 0>("c2048p32w8_c64"));
+  add(make_variant<ROLE_COL, 2048, 32, 8, 1, float2, 0>("c2048p32w8x_c64"));
+  add(make_variant<ROLE_COL, 2048, 32, 16, 1, float2, 0>("c2048p32w16x_c64"));
   add(make_variant<ROLE_COL, 4096, 8, 1, 0, float2, 0>("c4096p8w1_c64"));
   add(make_variant<ROLE_COL, 4096, 8, 2, 0, float2, 0>("c4096p8w2_c64"));
   add(make_variant<ROLE_COL, 4096, 8, 2, 1, float2, 0>("c4096p8w2x_c64"));
@@ -69,6 +70,7 @@ void add_variants_c64_col2(void (*add)(const Variant&)) {
   add(make_variant<ROLE_COL, 4096, 16, 2, 1, float2, 0>("c4096p16w2x_c64"));
   add(make_variant<ROLE_COL, 4096, 16, 4, 0, float2, 0>("c4096p16w4_c64"));
   add(make_variant<ROLE_COL, 4096, 16, 4, 1, float2, 0>("c4096p16w4x_c64"));
+  add(make_variant<ROLE_COL, 4096, 32, 8, 1, float2, 0>("c4096p32w8x_c64"));
   add(make_variant<ROLE_COL, 8192, 8, 1, 0, float2, 0>("c8192p8w1_c64"));
   add(make_variant<ROLE_COL, 8192, 8, 1, 1, float2, 0>("c8192p8w1x_c64"));
   add(make_variant<ROLE_COL, 8192, 16, 1, 0, float2, 0>("c8192p16w1_c64"));

@@ -184,3 +184,12 @@ def test_describe_levels_method(lib):
         with pytest.raises(capi.FFTError) as ei:
             capi.fft_describe(n, 1, dims, capi.FFT_C64, bad)
         assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT
+
+
+def test_describe_xcd_masks(lib):
+    for ok in ("xcd=0", "xcd=1", "xcd=01", "xcd=10"):
+        assert capi.fft_describe([1 << 20], 16, 1, capi.FFT_C64, ok)["passes"] == 2
+    assert capi.fft_describe([4096, 4096], 1, 2, capi.FFT_C64, "col3=1;xcd=101")["passes"] == 3
+    for bad in ("xcd=011", "xcd=2", "xcd=", "xcd=00000"):
+        with pytest.raises(capi.FFTError):
+            capi.fft_describe([1 << 20], 16, 1, capi.FFT_C64, bad)

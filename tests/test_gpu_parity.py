@@ -5,6 +5,7 @@ inputs and compares each transform with the oracle: rel-L2 <= 1e-6*log2(N)
 for the FP32 path.
 """
 import math
+import re
 
 import numpy as np
 import pytest
@@ -355,3 +356,43 @@ def test_2d_4096x4096_image_both_column_plans(dev, col3):
     # in place as well (no workspace needed for 2-D)
     got2 = run_c64(z, [4096, 4096], schedule=f"col3={col3}", inplace=True, dev=dev)
     assert np.array_equal(got, got2)
+
+
+LONG_COLUMNS = sorted(n for n in _variant_names(
+    lambda s: s.startswith("c") and "p32" in s and int(s[1:s.index("p")]) >= 2048))
+COL_TWIDDLE = sorted(n for n in _variant_names(lambda s: s.startswith("t")))
+
+
+@pytest.mark.parametrize("name", LONG_COLUMNS)
+def test_long_column_variants(dev, name):
+    # 32 points per lane down 2048- and 4096-long columns of a 2-D transform
+    L = int(name[1:name.index("p")])
+    dt = {"c64": capi.FFT_C64, "f16": capi.FFT_C16F, "bf16": capi.FFT_C16BF}[name.split("_")[1]]
+    if dt != capi.FFT_C64:
+        pytest.skip("complex64 variant test")
+    for c, inverse in ((64, False), (4, True)):  # 4 columns: a partial tile
+        x = workloads.normal_batch(L * c, 2, seed=L + c).reshape(2, L, c)
+        got = run_c64(x, [L, c], inverse=inverse, schedule=f"col3=0;col={name}", dev=dev)
+        ref = oracle.fft2(x.astype(np.complex64), inverse=inverse)
+        assert rel_l2_rows(got.reshape(2, -1), ref.reshape(2, -1), L * c).max() <= tol_fp32(L * c)
+
+
+@pytest.mark.parametrize("name", COL_TWIDDLE)
+def test_column_twiddle_variants(dev, name):
+    # every first column sub-pass variant in a three-pass 2-D plan
+    m = re.match(r"t(\d+)p(\d+)w(\d+)", name)
+    sq, w = int(m.group(1)), int(m.group(3))
+    dt = {"c64": capi.FFT_C64, "f16": capi.FFT_C16F, "bf16": capi.FFT_C16BF}[name.split("_")[1]]
+    if dt != capi.FFT_C64:
+        pytest.skip("complex64 variant test")
+    r, c, sched = sq * sq, max(w, 16), f"col3=1;colt={name}"
+    try:
+        capi.fft_describe([r, c], 2, 2, dt, sched)
+    except capi.FFTError:
+        # few rows: long rows, so a row tile of two rows exists
+        c, sched = 4096, sched + ";row=r4096p16w2_c64"
+        capi.fft_describe([r, c], 2, 2, dt, sched)
+    x = workloads.normal_batch(r * c, 2, seed=sq + w).reshape(2, r, c)
+    got = run_c64(x, [r, c], schedule=sched, dev=dev)
+    ref = oracle.fft2(x.astype(np.complex64))
+    assert rel_l2_rows(got.reshape(2, -1), ref.reshape(2, -1), r * c).max() <= tol_fp32(r * c)
