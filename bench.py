@@ -22,6 +22,9 @@ Other modes (used to make the rocprofv3 summaries under profiles/):
   --mode profile     run warmup + steps only (no CPU baseline), for
                      `rocprofv3 --kernel-trace --stats` and `--pmc` runs;
                      also runs one plain 256 MiB device copy (calibration).
+  --mode ablation    the method the paper improves on (Sec. 2.2: one global
+                     radix-2 kernel per butterfly level) against the LDS
+                     passes, forward 16 x 2^20, one JSON line
   --summarize-trace DIR         print the kernel-time summary of a trace run
   --summarize-pmc DIR_FETCH DIR_WRITE  print per-kernel HBM traffic
 """
@@ -68,7 +71,7 @@ def parse_args(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--mode", choices=["bench", "profile"], default="bench")
+    ap.add_argument("--mode", choices=["bench", "profile", "ablation"], default="bench")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--summarize-trace", metavar="DIR")
@@ -203,6 +206,40 @@ def cpu_baseline(x_np, seconds: float):
             "sample": f"{reps} x (forward + inverse of 16 x 2^20 complex, FP64 radix-2) in {el:.1f} s"}
 
 
+def ablation(capi, torch, lds_plan, sets, nsets, stream, reps):
+    """Forward 16 x 2^20 with the LDS passes and with one radix-2 kernel per
+    level (log2 N = 20 launches, each moving every point), timed alike."""
+    lev = capi.fft_plan_ex([N], BATCH, 1, capi.FFT_C64, capi.FFT_FORWARD, "method=levels")
+    out = {"ablation": "per-level global-memory radix-2 (paper Sec. 2.2) vs LDS-resident passes",
+           "workload": "1-D C2C forward, N=2^20, batch 16, complex64, N(0,1) seed 1",
+           "reps": reps}
+    res = {}
+    for name, plan in (("lds", lds_plan), ("levels", lev)):
+        info = capi.fft_plan_info(plan)
+        for i in range(3):
+            xi, yi, _ = sets[i % nsets]
+            capi.fft_exec(plan, xi.data_ptr(), yi.data_ptr(), stream)
+        torch.cuda.synchronize()
+        capi.fft_profile_enable(plan, reps)
+        for i in range(reps):
+            xi, yi, _ = sets[i % nsets]
+            capi.fft_exec(plan, xi.data_ptr(), yi.data_ptr(), stream)
+        torch.cuda.synchronize()
+        capi.fft_profile_collect(plan)
+        us = sum(1e3 * capi.fft_profile_read(plan, p)[0] / reps for p in range(info["passes"]))
+        moved = sum(info["bytes_pass"])
+        res[name] = yi.clone()
+        out[name] = {"us": round(us, 2), "launches": N.bit_length() - 1 if name == "levels" else info["passes"],
+                     "GFLOPs": round(info["flops"] / (us * 1e-6) / 1e9, 1),
+                     "bytes_moved": moved, "GBps": round(moved / (us * 1e-6) / 1e9, 1)}
+        capi.fft_profile_enable(plan, 0)
+    out["speedup_lds_over_levels"] = round(out["levels"]["us"] / out["lds"]["us"], 2)
+    out["rel_l2_levels_vs_lds"] = (torch.linalg.vector_norm(res["levels"] - res["lds"]) /
+                                   torch.linalg.vector_norm(res["lds"])).item()
+    capi.fft_destroy(lev)
+    return out
+
+
 def main(argv=None) -> int:
     args = parse_args(argv)
     if args.summarize_trace:
@@ -252,6 +289,10 @@ def main(argv=None) -> int:
         step(i)
     torch.cuda.synchronize()
     print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    if args.mode == "ablation":
+        print(json.dumps(ablation(capi, torch, fwd, sets, nsets, stream, args.steps)))
+        return 0
 
     if args.mode == "profile":
         for i in range(args.steps):
