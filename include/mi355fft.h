@@ -132,6 +132,9 @@ int fft_plan_many(const int64_t *sizes, int64_t count, int dtype, int direction,
  *   'pass2=' t         lengths of at least 2^t use two passes (1 <= t <= 1 +
  *                      log2 of the longest one-tile length, which is the default)
  *   'order=' bigfirst|given   order of the work queue
+ *   'pipe=' 0|1        1: one workgroup per CU that loads its next item while
+ *                      it transforms the current one (compiled for p=16,
+ *                      threads=512), items assigned round-robin in queue order
  *   'lag=' k           0 (default): every first-pass item ahead of every
  *                      second-pass item; k > 0: the second-pass items of the
  *                      i-th two-pass transform follow the first-pass items of

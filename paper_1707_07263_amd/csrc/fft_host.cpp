@@ -600,9 +600,13 @@ void many_free(ManyPlan& mp) {
   if (mp.d_items) hipFree(mp.d_items);
   if (mp.d_xf) hipFree(mp.d_xf);
   if (mp.d_order) hipFree(mp.d_order);
+  if (mp.d_order_off) hipFree(mp.d_order_off);
+  if (mp.d_tw_img) hipFree(mp.d_tw_img);
   mp.d_items = nullptr;
   mp.d_xf = nullptr;
   mp.d_order = nullptr;
+  mp.d_order_off = nullptr;
+  mp.d_tw_img = nullptr;
   mp.active = false;
 }
 
@@ -613,6 +617,7 @@ namespace {
 struct ManyOptions {
   int P = 16, threads = 256, pass2 = 0;  // pass2 0: two passes above the longest one-tile length
   bool given_order = false;
+  int pipe = 0;  // 1: the software-pipelined kernel (one workgroup per CU)
   // 0: every first-pass tile ahead of every second-pass tile; k > 0: the
   // second-pass tiles of split transform i follow the first-pass tiles of
   // split transform i + k, so its intermediate is still in the last-level
@@ -647,6 +652,9 @@ int parse_many_schedule(const char* s, ManyOptions* o) {
     else if (key == "pass2") {
       if (v < 1) return FFT_ERR_INVALID_ARGUMENT;
       o->pass2 = (int)v;
+    } else if (key == "pipe") {
+      if (v != 0 && v != 1) return FFT_ERR_INVALID_ARGUMENT;
+      o->pipe = (int)v;
     } else if (key == "lag") {
       if (v < 0 || v > (1 << 24)) return FFT_ERR_INVALID_ARGUMENT;
       o->lag = (int)v;
@@ -1092,7 +1100,8 @@ int build_many(const int64_t* sizes, int64_t count, int dtype, int direction, co
   if (parse_many_schedule(schedule, &opt)) return FFT_ERR_INVALID_ARGUMENT;
   for (int i = 0; i < many_variant_count(); ++i) {
     const ManyVariant* v = many_variant(i);
-    if (v->dtype == dtype && v->P == opt.P && v->threads == opt.threads) mb->var = v;
+    if (v->dtype == dtype && v->P == opt.P && v->threads == opt.threads && v->pipe == opt.pipe)
+      mb->var = v;
   }
   if (!mb->var) return FFT_ERR_INVALID_ARGUMENT;
   const int max_tile = std::min(kManyMaxLg, ilog2_64((int64_t)opt.threads * opt.P));
@@ -1272,11 +1281,19 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
     auto it = inter.find(x.lg);
     if (it == inter.end()) {
       const int64_t N = (int64_t)1 << x.lg;
-      const int64_t lo = tb.add((int64_t)1 << x.lg1, 0, N, 1);
-      tb.add((int64_t)1 << (x.lg - x.lg1), 0, N, (int64_t)1 << x.lg1);
+      const int64_t N1 = (int64_t)1 << x.lg1, N2 = N >> x.lg1;
+      const int64_t lo = tb.add(N1, 0, N, 1);
+      tb.add(N2, 0, N, N1);
+      // step rows W_N^{n2*q*T}, T = N1/P: entry n2*P + q
+      const int pp = (int)std::min<int64_t>(opt.P, N1);
+      tb.add(N2 * pp, pp, N, N1 / pp);
       it = inter.emplace(x.lg, lo).first;
     }
     x.tw_lo = it->second;
+    {
+      const int64_t N1 = (int64_t)1 << x.lg1, N2 = ((int64_t)1 << x.lg) >> x.lg1;
+      x.tw_step = x.tw_lo + N1 + N2;
+    }
   }
   int rc = upload_tables(p, tb, max_lg >= kGpuTwiddleMinLog2);
   if (rc) {
@@ -1298,6 +1315,9 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
   rc = upload((void**)&mp.d_items, items.data(), items.size() * sizeof(ManyItem));
   if (!rc) rc = upload((void**)&mp.d_xf, xf.data(), xf.size() * sizeof(ManyXform));
   if (!rc) rc = upload((void**)&mp.d_order, order.data(), order.size() * sizeof(int32_t));
+  std::vector<int64_t> order_off(order.size());
+  for (size_t i = 0; i < order.size(); ++i) order_off[i] = xf[order[i]].off;
+  if (!rc) rc = upload((void**)&mp.d_order_off, order_off.data(), order_off.size() * sizeof(int64_t));
   if (rc) {
     fft_destroy(p);
     return rc;
@@ -1318,8 +1338,38 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
   a.items = mp.d_items;
   a.xf = mp.d_xf;
   a.order = mp.d_order;
+  a.order_off = mp.d_order_off;
   a.tw = mp.d_tw;
   for (int lg = 0; lg <= kManyMaxLg; ++lg) a.stage_off[lg] = soff[lg];
+  a.tw_used = 0;
+  for (int lg = 1; lg <= max_tile; ++lg)
+    if (used[lg]) a.tw_used |= 1 << lg;
+  if (var->pipe) {
+    // the pipelined kernel's LDS image of the stage twiddles, gathered once
+    std::vector<int32_t> map;
+    const int len = many_tw_image_map(a.stage_off, a.tw_used, opt.P, &map);
+    int32_t* d_map = nullptr;
+    rc = upload((void**)&d_map, map.data(), map.size() * sizeof(int32_t));
+    if (!rc) {
+      e = hipMalloc((void**)&mp.d_tw_img, std::max<size_t>(map.size(), 1) * sizeof(float2));
+      if (e != hipSuccess) {
+        mp.d_tw_img = nullptr;
+        rc = e == hipErrorOutOfMemory ? FFT_ERR_NO_MEMORY : hip_fail(e);
+      }
+    }
+    if (!rc) {
+      e = launch_gather_f2(mp.d_tw_img, p->d_tables, d_map, (int)map.size(), nullptr);
+      if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+      if (e != hipSuccess) rc = hip_fail(e);
+    }
+    if (d_map) hipFree(d_map);
+    if (rc) {
+      fft_destroy(p);
+      return rc;
+    }
+    a.tw_img = mp.d_tw_img;
+    a.tw_img_len = len;
+  }
   a.n_items = (int32_t)items.size();
   a.n_xforms = (int32_t)count;
   a.wait_ticks = kManyWaitDefaultUs * 100;

@@ -43,13 +43,11 @@ __device__ __forceinline__ void many_tile(const ManyArgs& a, const ManyItem& d, 
   // line addressing of the load
   int64_t ibase = 0, ielem = 1;
   bool ok = true;
-  int xid = d.a;
   if (d.kind == MANY_SINGLE) {
     ok = m < d.b;
-    xid = ok ? a.order[d.a + m] : 0;
-    ibase = a.xf[xid].off;
+    ibase = a.order_off[ok ? d.a + m : d.a];
   } else {
-    const ManyXform x = a.xf[xid];
+    const ManyXform x = a.xf[d.a];
     const int64_t N1 = (int64_t)1 << x.lg1, N2 = (int64_t)1 << (x.lg - x.lg1);
     const int64_t line = (int64_t)d.b * W + m;
     if (d.kind == MANY_A) {
@@ -82,11 +80,10 @@ __device__ __forceinline__ void many_tile(const ManyArgs& a, const ManyItem& d, 
   ok = true;
   if (d.kind == MANY_SINGLE) {
     ok = m < d.b;
-    xid = ok ? a.order[d.a + m] : 0;
-    obase = a.xf[xid].off;
+    obase = a.order_off[ok ? d.a + m : d.a];
     scale = a.use_scale ? a.scale : (a.inverse ? 1.f / (float)L : 1.f);
   } else {
-    const ManyXform x = a.xf[xid];
+    const ManyXform x = a.xf[d.a];
     const int64_t N1 = (int64_t)1 << x.lg1, N2 = (int64_t)1 << (x.lg - x.lg1);
     const int64_t line = (int64_t)d.b * W + m;
     line_st = (uint32_t)line;
@@ -210,6 +207,417 @@ __global__ void __launch_bounds__(NT) k_many(ManyArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Software-pipelined variant: one workgroup per CU.  While a workgroup runs
+// the butterflies of one item, the loads of its next item are in flight.
+// Everything it reads between issuing those loads and consuming them comes
+// from LDS: the stage twiddles of every tile length the plan uses are copied
+// there at launch (vector-memory counters retire in order, so waiting on any
+// later global load would also wait on the prefetch).
+// ---------------------------------------------------------------------------
+
+// LDS offset of the stage twiddles of a 2^LG tile (LG >= 1).
+template <int P, int LG>
+struct ManyTwOff {
+  static constexpr int value = ManyTwOff<P, LG - 1>::value + TwLds<(1 << (LG - 1)), P>::SIZE;
+};
+template <int P>
+struct ManyTwOff<P, 1> {
+  static constexpr int value = 0;
+};
+template <int P>
+constexpr int many_tw_total() { return ManyTwOff<P, kManyMaxLg + 1>::value; }
+
+template <int P, int LG>
+void many_tw_map_lg(const int64_t* stage_off, int32_t tw_used, std::vector<int32_t>& map, int& len) {
+  if constexpr (LG <= kManyMaxLg) {
+    if ((tw_used >> LG) & 1) {
+      using S = Sched<(1 << LG), P>;
+      using TL = TwLds<(1 << LG), P>;
+      const int base = ManyTwOff<P, LG>::value;
+      for (int s = 1; s < S::S; ++s)
+        for (int k = 0; k < S::ns(s); ++k)
+          for (int r = 0; r < S::radix(s); ++r)
+            map[base + TL::off(s) + k * TL::rp(s) + r] = (int32_t)(stage_off[LG] + S::off(s) + k * S::radix(s) + r);
+      len = base + TL::SIZE;
+    }
+    many_tw_map_lg<P, LG + 1>(stage_off, tw_used, map, len);
+  }
+}
+
+int many_tw_image_map(const int64_t* stage_off, int32_t tw_used, int P, std::vector<int32_t>* map) {
+  if (P != 16) return 0;
+  map->assign(many_tw_total<16>(), -1);
+  int len = 0;
+  many_tw_map_lg<16, 1>(stage_off, tw_used, *map, len);
+  return len;
+}
+
+__global__ void k_gather_f2(float2* dst, const float2* src, const int32_t* map, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = map[i] >= 0 ? src[map[i]] : make_float2(0.f, 0.f);
+}
+
+hipError_t launch_gather_f2(float2* dst, const float2* src, const int32_t* map, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_f2, dim3((n + 255) / 256), dim3(256), 0, s, dst, src, map, n);
+  return hipGetLastError();
+}
+
+// What the pipelined kernel loads ahead for one item: its points, the
+// element offset of each lane's line (one-pass items), and for a split's
+// first pass the inter-pass twiddle inputs: the lane's base W_N^{line*t}
+// (lo/hi factors) and the tile's step rows W_N^{line*q*T} (W*PP entries,
+// up to two per lane).
+template <int P>
+struct ManyPre {
+  float2 v[P];
+  float2 rown[2];
+  float2 lon, hin;
+  int64_t base;
+};
+
+template <int P, int NT>
+__host__ __device__ constexpr bool many_step_rows(int lg) {
+  // W*PP <= 2*NT, with PP = min(P, L), T = L/PP, W = NT/T
+  return ((int64_t)NT << (2 * (lg < ilog2(P) ? lg : ilog2(P)))) >> lg <= 2 * NT;
+}
+
+// Issue the loads of item d (length 2^lg >= 2): the same lines and lane
+// mapping as the compute step below uses, with runtime sizes.
+template <int P, int NT, typename TS>
+__device__ __forceinline__ void many_prefetch(const ManyArgs& a, const ManyItem& d, const ManyXform& x,
+                                              ManyPre<P>& pre, int tid) {
+  const int lg = d.lg;
+  const int lpp = lg < ilog2(P) ? lg : ilog2(P);
+  const int PP = 1 << lpp;
+  const int lt = lg - lpp;                    // log2 T
+  const int lw = ilog2(NT) - lt;              // log2 W
+  const bool mfast = d.kind != MANY_SINGLE;
+  const int m = mfast ? (tid & ((1 << lw) - 1)) : (tid >> lt);
+  const int t = mfast ? (tid >> lw) : (tid & ((1 << lt) - 1));
+  const TS* src = reinterpret_cast<const TS*>(d.kind == MANY_B ? a.out : a.in);
+  int64_t ibase = 0, ielem = 1;
+  bool ok = true;
+  if (d.kind == MANY_SINGLE) {
+    ok = m < d.b;
+    ibase = a.order_off[ok ? d.a + m : d.a];
+    pre.base = ibase;
+  } else {
+    const int64_t line = ((int64_t)d.b << lw) + m;
+    const int64_t n1 = (int64_t)1 << x.lg1, n2 = (int64_t)1 << (x.lg - x.lg1);
+    ok = line < (d.kind == MANY_A ? n2 : n1);
+    ibase = x.off + line;
+    ielem = d.kind == MANY_A ? n2 : n1;
+    if (d.kind == MANY_A && many_step_rows<P, NT>(lg)) {
+      const int64_t line0 = (int64_t)d.b << lw;
+      const int wpp = 1 << (lw + lpp);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int i = tid + k * NT;
+        if (i < wpp) {
+          const int64_t ln = line0 + (i >> lpp) < n2 ? line0 + (i >> lpp) : n2 - 1;
+          pre.rown[k] = a.tw[x.tw_step + (ln << lpp) + (i & (PP - 1))];
+        }
+      }
+      // the store mapping is point-fastest: line m_st = tid / T, point t_st = tid % T
+      const int64_t lst = line0 + (tid >> lt);
+      const uint32_t jb = (uint32_t)(lst < n2 ? lst : n2 - 1) * (uint32_t)(tid & ((1 << lt) - 1));
+      pre.lon = a.tw[x.tw_lo + (jb & (uint32_t)(n1 - 1))];
+      pre.hin = a.tw[x.tw_lo + n1 + (jb >> x.lg1)];
+    }
+  }
+  const int64_t step = ielem << lt;
+  const TS* p0 = src + ibase + (int64_t)t * ielem;
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+    if (q < PP) pre.v[q] = ok ? load_c(p0 + q * step) : make_float2(0.f, 0.f);
+}
+
+// Butterflies and store of one item whose points are in v.  `base` is the
+// element offset of the lane's line for one-pass items; for a split's first
+// pass with step rows, `tw_base` is the lane's W_N^{line*t} and rowl holds
+// the tile's W_N^{line*q*T}.  `between` runs after the butterflies and
+// before the stores (workgroup-uniform).
+template <int L, int P, int NT, typename TS, typename F>
+__device__ __forceinline__ void many_body(const ManyArgs& a, const ManyItem& d, float2* v, float2* xch,
+                                          const float2* twl, const float2* rowl, float2 tw_base,
+                                          int64_t base, int tid, F&& between) {
+  using S = Sched<L, P>;
+  constexpr int T = S::T;
+  constexpr int PP = S::PP;
+  constexpr int W = NT / T;
+  constexpr bool kRows = many_step_rows<P, NT>(ilog2(L));
+  static_assert(W >= 1 && W * T == NT, "tile must fill the workgroup");
+  const bool mfast_in = d.kind != MANY_SINGLE;
+  const bool mfast_out = d.kind == MANY_B;
+  int m = mfast_in ? tid % W : tid / T;
+  int t = mfast_in ? tid / W : tid % T;
+  const int m_st = mfast_out ? tid % W : tid / T;
+  const int t_st = mfast_out ? tid / W : tid % T;
+  const bool first = d.kind != MANY_B;
+  const bool last = d.kind != MANY_A;
+  const uint32_t sgn_in = (first && a.inverse) ? 0x80000000u : 0u;
+#pragma unroll
+  for (int q = 0; q < PP; ++q) v[q].y = __uint_as_float(__float_as_uint(v[q].y) ^ sgn_in);
+
+  run_stages<L, P, W, 0, 1>(v, xch, m, t, m_st, t_st, mfast_in != mfast_out, twl);
+  between();
+
+  TS* dst = reinterpret_cast<TS*>(a.out);
+  int64_t obase = 0, oelem = 1;
+  float scale = 1.f;
+  int64_t twl_off = 0;
+  int lg1 = 0;
+  uint32_t line_st = 0;
+  bool ok = true;
+  if (d.kind == MANY_SINGLE) {
+    ok = m < d.b;
+    obase = base;
+    scale = a.use_scale ? a.scale : (a.inverse ? 1.f / (float)L : 1.f);
+  } else {
+    const ManyXform x = a.xf[d.a];
+    const int64_t N1 = (int64_t)1 << x.lg1, N2 = (int64_t)1 << (x.lg - x.lg1);
+    const int64_t line = (int64_t)d.b * W + m;
+    line_st = (uint32_t)line;
+    if (d.kind == MANY_A) {
+      ok = line < N2;
+      obase = x.off + line * N1;  // T[n2*N1 + k1]
+      twl_off = x.tw_lo;
+      lg1 = x.lg1;
+      scale = (a.inverse && !a.use_scale) ? 1.f / (float)N1 : 1.f;
+    } else {
+      ok = line < N1;
+      obase = x.off + line;  // X[k1 + N1*k2]
+      oelem = N1;
+      scale = a.use_scale ? a.scale : (a.inverse ? 1.f / (float)N2 : 1.f);
+    }
+  }
+  const uint32_t sgn_out = (last && a.inverse) ? 0x80000000u : 0u;
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int e = t + q * T;
+    float2 y = v[q];
+    if (d.kind == MANY_A) {
+      if constexpr (kRows) {
+        y = cmul(y, cmul(tw_base, rowl[m * PP + q]));
+      } else {
+        const uint32_t jj = line_st * (uint32_t)e;
+        const float2* lo = a.tw + twl_off;
+        const float2* hi = lo + ((int64_t)1 << lg1);
+        y = cmul(y, cmul(hi[jj >> lg1], lo[jj & ((1u << lg1) - 1u)]));
+      }
+    }
+    y = cscale(y, scale);
+    y.y = __uint_as_float(__float_as_uint(y.y) ^ sgn_out);
+    if (ok) store_c(dst + obase + (int64_t)e * oelem, y);
+  }
+}
+
+// Items are taken in queue order, workgroup g taking items g, g + G, g + 2G
+// (G resident workgroups): the tiles are of equal size, and the index and
+// descriptors of the next item are known without a round trip to a shared
+// counter (measured: a shared counter read two items ahead was slower).
+// Forward progress: a workgroup runs its items in order, waits only for a
+// second-pass item's first pass (earlier in the queue) and releases its own
+// finished first-pass tiles before any wait, so the unfinished item of
+// lowest index always has its dependencies released and is being run.
+template <typename TS, int P, int NT>
+__global__ void __launch_bounds__(NT, 1) k_many_pipe(ManyArgs a) {
+  static_assert(NT * P >= (1 << kManyMaxLg), "every tile length runs the barriers of `between`");
+  constexpr int XN = many_lds_max<P, NT>();
+  constexpr int TWN = many_tw_total<P>();
+  __shared__ float2 lds[XN + TWN + 2 * NT];
+  __shared__ int s_ready, s_last;
+  float2* xch = lds;
+  float2* twl = lds + XN;
+  float2* rowl = lds + XN + TWN;
+  const int tid = threadIdx.x;
+  int* exits = a.ws + 1;
+  int* watchdog = a.ws + 2;
+  int* done = a.ws + kManyWsHeader;
+
+  // Thread 0: bounded wait for transform x's first pass (same protocol as
+  // k_many: relaxed polls, one acquire, watchdog flag on expiry).
+  auto wait_released = [&](int x) {
+    const int need = a.xf[x].nA;
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    while (__hip_atomic_load(&done[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+      __builtin_amdgcn_s_sleep(8);
+      if (__builtin_amdgcn_s_memrealtime() - t0 > (uint64_t)a.wait_ticks) {
+        atomicOr(watchdog, 1);
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  };
+  // Thread 0: whether item `it` can be loaded now (a second-pass item whose
+  // first pass has released; acquire if so), 1 for other items.
+  auto check = [&](int it) -> int {
+    if (it >= a.n_items) return 1;
+    const ManyItem di = a.items[it];
+    if (di.kind != MANY_B) return 1;
+    if (__hip_atomic_load(&done[di.a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < a.xf[di.a].nA) return 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return 1;
+  };
+
+  // stage twiddles: one contiguous copy of the plan's LDS image (all loads
+  // issued before the first store)
+  {
+    constexpr int K = (TWN + NT - 1) / NT;
+    float2 tmp[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (tid + k * NT < a.tw_img_len) tmp[k] = a.tw_img[tid + k * NT];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (tid + k * NT < a.tw_img_len) twl[tid + k * NT] = tmp[k];
+  }
+
+  const int G = (int)gridDim.x;
+  int cur = (int)blockIdx.x;
+  ManyItem d{};
+  ManyPre<P> pre;
+  pre.base = 0;
+  if (cur < a.n_items) {
+    d = a.items[cur];
+    if (d.kind == MANY_B && tid == 0) wait_released(d.a);
+  }
+  __syncthreads();  // stage twiddles visible; thread 0's acquire before the loads
+  if (cur < a.n_items && d.lg >= 1)
+    many_prefetch<P, NT, TS>(a, d, d.kind != MANY_SINGLE ? a.xf[d.a] : ManyXform{}, pre, tid);
+  int nxt = cur + G;
+  if (tid == 0) s_ready = check(nxt);
+  __syncthreads();
+  int ready = s_ready;
+  // descriptors of the next item, read one item ahead
+  ManyItem dn{};
+  ManyXform xn{};
+  if (nxt < a.n_items) {
+    dn = a.items[nxt];
+    if (dn.kind != MANY_SINGLE) xn = a.xf[dn.a];
+  }
+  // An A tile's release waits for its stores; it is deferred to the next
+  // item's barrier after the butterflies, by which time they have drained.
+  int pending = -1;
+
+  while (cur < a.n_items) {
+    float2 v[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) v[q] = pre.v[q];
+    const int64_t base = pre.base;
+    float2 tw_base = make_float2(1.f, 0.f);
+    if (d.kind == MANY_A && d.lg >= 1 && many_step_rows<P, NT>(d.lg)) {
+      lds_barrier();  // the previous tile's reads of the step rows are done
+      const int lpp = d.lg < ilog2(P) ? d.lg : ilog2(P);
+      const int wpp = (NT << (2 * lpp)) >> d.lg;  // W * PP <= 2 * NT
+      rowl[tid] = pre.rown[0];
+      if (tid + NT < wpp) rowl[tid + NT] = pre.rown[1];
+      tw_base = cmul(pre.hin, pre.lon);
+    }
+    const bool has_next = nxt < a.n_items;
+    if (has_next && ready && dn.lg >= 1) many_prefetch<P, NT, TS>(a, dn, xn, pre, tid);
+    const int nxt2 = nxt + G;
+    ManyItem dn2{};
+    ManyXform xn2{};
+    if (nxt2 < a.n_items) {
+      dn2 = a.items[nxt2];
+      if (dn2.kind != MANY_SINGLE) xn2 = a.xf[dn2.a];
+    }
+    int ready2 = 1;
+    // after the butterflies: every wave's older stores and this prefetch
+    // have landed; release the previous A tile, look at the item after next
+    auto between = [&]() {
+      __syncthreads();
+      if (tid == 0) {
+        if (pending >= 0)
+          __hip_atomic_fetch_add(&done[pending], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        s_ready = has_next ? check(nxt2) : 1;
+      }
+      pending = -1;
+      __syncthreads();  // thread 0's acquire precedes every lane's later loads
+      ready2 = s_ready;
+    };
+
+    switch (d.lg) {
+      case 0: between(); many_tile1<NT, TS>(a, d, tid); break;
+      case 1: many_body<2, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 1>::value, rowl, tw_base, base, tid, between); break;
+      case 2: many_body<4, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 2>::value, rowl, tw_base, base, tid, between); break;
+      case 3: many_body<8, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 3>::value, rowl, tw_base, base, tid, between); break;
+      case 4: many_body<16, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 4>::value, rowl, tw_base, base, tid, between); break;
+      case 5: many_body<32, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 5>::value, rowl, tw_base, base, tid, between); break;
+      case 6: many_body<64, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 6>::value, rowl, tw_base, base, tid, between); break;
+      case 7: many_body<128, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 7>::value, rowl, tw_base, base, tid, between); break;
+      case 8: many_body<256, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 8>::value, rowl, tw_base, base, tid, between); break;
+      case 9: many_body<512, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 9>::value, rowl, tw_base, base, tid, between); break;
+      case 10:
+        if constexpr (NT * P >= 1024)
+          many_body<1024, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 10>::value, rowl, tw_base, base, tid, between);
+        break;
+      case 11:
+        if constexpr (NT * P >= 2048)
+          many_body<2048, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 11>::value, rowl, tw_base, base, tid, between);
+        break;
+      case 12:
+        if constexpr (NT * P >= 4096)
+          many_body<4096, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 12>::value, rowl, tw_base, base, tid, between);
+        break;
+      default: between(); break;
+    }
+    if (d.kind == MANY_A) pending = d.a;
+    if (has_next && !ready) {
+      // its first pass was still running at the check: release ours (it may
+      // be one of them), wait, then load
+      __syncthreads();
+      if (tid == 0) {
+        if (pending >= 0)
+          __hip_atomic_fetch_add(&done[pending], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        wait_released(dn.a);
+      }
+      pending = -1;
+      __syncthreads();
+      if (dn.lg >= 1) many_prefetch<P, NT, TS>(a, dn, xn, pre, tid);
+    }
+    cur = nxt;
+    d = dn;
+    nxt = nxt2;
+    dn = dn2;
+    xn = xn2;
+    ready = ready2;
+  }
+  if (pending >= 0) {
+    __syncthreads();
+    if (tid == 0) __hip_atomic_fetch_add(&done[pending], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // The last workgroup out resets the queue state for the next launch.
+  if (tid == 0) {
+    const int fin = __hip_atomic_fetch_add(exits, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = fin == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_last) {
+    for (int i = tid; i < a.n_xforms; i += NT) done[i] = 0;
+    if (tid == 0) {
+      a.ws[0] = 0;
+      *exits = 0;
+    }
+  }
+}
+
+template <typename TS, int P, int NT>
+hipError_t launch_many_pipe(const ManyArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_many_pipe<TS, P, NT>), dim3(grid), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename TS, int P, int NT>
+int blocks_many_pipe() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_many_pipe<TS, P, NT>, NT, 0) != hipSuccess) return 0;
+  return n;
+}
+
 template <typename TS, int P, int NT>
 hipError_t launch_many(const ManyArgs& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL((k_many<TS, P, NT>), dim3(grid), dim3(NT), 0, s, a);
@@ -223,13 +631,15 @@ int blocks_many() {
   return n;
 }
 
-#define MANY_VARIANT(TS, DT, P, NT) {DT, P, NT, &launch_many<TS, P, NT>, &blocks_many<TS, P, NT>}
+#define MANY_VARIANT(TS, DT, P, NT) {DT, P, NT, 0, &launch_many<TS, P, NT>, &blocks_many<TS, P, NT>}
+#define MANY_PIPE(TS, DT, P, NT) {DT, P, NT, 1, &launch_many_pipe<TS, P, NT>, &blocks_many_pipe<TS, P, NT>}
 
 static const ManyVariant kManyVariants[] = {
     MANY_VARIANT(float2, DT_C64, 16, 256),   MANY_VARIANT(float2, DT_C64, 8, 256),
     MANY_VARIANT(float2, DT_C64, 16, 512),   MANY_VARIANT(__half2, DT_C16F, 16, 256),
     MANY_VARIANT(__half2, DT_C16F, 8, 256),  MANY_VARIANT(c16bf, DT_C16BF, 16, 256),
-    MANY_VARIANT(c16bf, DT_C16BF, 8, 256),
+    MANY_VARIANT(c16bf, DT_C16BF, 8, 256),   MANY_PIPE(float2, DT_C64, 16, 512),
+    MANY_PIPE(__half2, DT_C16F, 16, 512),    MANY_PIPE(c16bf, DT_C16BF, 16, 512),
 };
 
 int many_variant_count() { return (int)(sizeof(kManyVariants) / sizeof(kManyVariants[0])); }

@@ -12,6 +12,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace mfft {
 
 enum ManyKind { MANY_SINGLE = 0, MANY_A = 1, MANY_B = 2 };
@@ -31,6 +33,7 @@ struct ManyItem {
 struct ManyXform {
   int64_t off;
   int64_t tw_lo;
+  int64_t tw_step;  // [N2][P] entries W_N^{n2*q*(N1/P)} (first pass of a split, N1 >= P)
   int32_t lg, lg1, nA, pad;
 };
 
@@ -42,6 +45,7 @@ struct ManyArgs {
   const ManyItem* items;
   const ManyXform* xf;
   const int32_t* order;
+  const int64_t* order_off;           // element offset of transform order[i]
   const float2* tw;                   // base of the plan's tables
   int64_t stage_off[kManyMaxLg + 1];  // stage table of a 2^lg tile
   int32_t n_items, n_xforms;
@@ -50,15 +54,28 @@ struct ManyArgs {
   int32_t use_scale;                  // 0: per-transform default (1 or 1/N)
   int32_t inverse;
   int64_t wait_ticks;  // bound of one dependency wait, 100 MHz ticks
+  int32_t tw_used;     // bit lg set: the plan has 2^lg tiles (stage table present)
+  // pipelined kernel: the stage twiddles of every used length, laid out as
+  // the kernel keeps them in LDS (copied there contiguously at launch)
+  const float2* tw_img;
+  int32_t tw_img_len;
 };
 
 constexpr int kManyWsHeader = 4;  // ints before the per-transform counters
 
 struct ManyVariant {
   int dtype, P, threads;
+  int pipe;  // 1: software-pipelined, one workgroup per CU
   hipError_t (*launch)(const ManyArgs&, int grid, hipStream_t);
   int (*max_blocks_per_cu)();
 };
+
+// LDS image of the pipelined kernel's stage twiddles (P points per lane):
+// entry i holds table element map[i] (an index into the plan's twiddle
+// table), or nothing (-1: row padding, unused lengths).  Returns the number
+// of entries the kernel copies (up to the longest used length).
+int many_tw_image_map(const int64_t* stage_off, int32_t tw_used, int P, std::vector<int32_t>* map);
+hipError_t launch_gather_f2(float2* dst, const float2* src, const int32_t* map, int n, hipStream_t s);
 
 // Compiled persistent-kernel variants (storage type x points per lane x
 // workgroup size).
@@ -72,7 +89,9 @@ struct ManyPlan {
   ManyItem* d_items = nullptr;
   ManyXform* d_xf = nullptr;
   int32_t* d_order = nullptr;
+  int64_t* d_order_off = nullptr;
   float2* d_tw = nullptr;
+  float2* d_tw_img = nullptr;
   ManyArgs args{};
   int64_t count = 0, n_items = 0;
   int64_t points = 0, pass_points = 0, packed_bytes = 0;

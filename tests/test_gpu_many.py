@@ -77,8 +77,9 @@ def test_uneven_512_complex64(dev, which):
     assert np.all(per_transform_errors(inv, ref_inv, sizes) <= tol)
 
 
+@pytest.mark.parametrize("pipe", [False, True])
 @pytest.mark.parametrize("dt", ["f16", "bf16"])
-def test_uneven_512_16bit(dev, dt):
+def test_uneven_512_16bit(dev, dt, pipe):
     code, tname = DT16[dt]
     tdt = getattr(torch, tname)
     sizes, packed = workloads.uneven_batch(512, 8, 16, seed=3)
@@ -87,7 +88,7 @@ def test_uneven_512_16bit(dev, dt):
     out = torch.empty_like(xt)
     from paper_1707_07263_amd import autotune
     h = capi.fft_plan_many_ex(list(sizes), code, capi.FFT_FORWARD,
-                              autotune.many_schedule_for(sizes, code))
+                              "pipe=1;threads=512" if pipe else autotune.many_schedule_for(sizes, code))
     try:
         capi.fft_exec(h, xt.data_ptr(), out.data_ptr(), torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
@@ -104,7 +105,9 @@ def test_uneven_512_16bit(dev, dt):
 
 
 @pytest.mark.parametrize("schedule", [None, "p=8", "pass2=10", "pass2=13;order=given",
-                                      "threads=512", "pass2=1", "lag=1", "lag=3;pass2=9"])
+                                      "threads=512", "pass2=1", "lag=1", "lag=3;pass2=9",
+                                      "pipe=1;threads=512", "pipe=1;threads=512;pass2=1",
+                                      "pipe=1;threads=512;pass2=9;lag=2"])
 def test_many_schedules_and_small_sizes(dev, schedule):
     # every length 2^0..2^16 twice, shuffled, under each compiled schedule
     g = workloads.rng(77)
@@ -119,7 +122,7 @@ def test_many_schedules_and_small_sizes(dev, schedule):
     assert np.all(errs <= tol), (schedule, float((errs / tol).max()))
 
 
-@pytest.mark.parametrize("schedule", ["lag=0", "lag=2", "threads=512;lag=1"])
+@pytest.mark.parametrize("schedule", ["lag=0", "lag=2", "threads=512;lag=1", "pipe=1;threads=512"])
 def test_many_16x2p20_lagged_queue(dev, schedule):
     # sixteen 2^20-point transforms in one launch, second passes interleaved
     # with later first passes
@@ -154,12 +157,13 @@ def test_many_inverse_scale_and_repeat(dev):
         capi.fft_destroy(h)
 
 
-def test_many_graph_capture_replay(dev):
+@pytest.mark.parametrize("schedule", [None, "pipe=1;threads=512"])
+def test_many_graph_capture_replay(dev, schedule):
     sizes, packed = workloads.uneven_batch(128, 8, 16, seed=31)
     xt = to_gpu_c64(packed, dev)
     out = torch.zeros_like(xt)
     eager = torch.empty_like(xt)
-    h = capi.fft_plan_many(list(sizes), capi.FFT_C64, capi.FFT_FORWARD)
+    h = capi.fft_plan_many_ex(list(sizes), capi.FFT_C64, capi.FFT_FORWARD, schedule)
     try:
         st = torch.cuda.current_stream().cuda_stream
         capi.fft_exec(h, xt.data_ptr(), eager.data_ptr(), st)
@@ -186,7 +190,8 @@ def test_many_graph_capture_replay(dev):
         capi.fft_destroy(h)
 
 
-def test_many_bounded_wait_forced_from_host(dev):
+@pytest.mark.parametrize("schedule", [None, "pipe=1;threads=512"])
+def test_many_bounded_wait_forced_from_host(dev, schedule):
     # A wait bound of 1 us makes a second-pass tile give up early when its
     # first-pass tiles are still running; the kernel must still finish, the
     # flag must report it (when it happened) and a normal run afterwards must
@@ -195,7 +200,7 @@ def test_many_bounded_wait_forced_from_host(dev):
     packed = workloads.normal_batch(1 << 16, 64, seed=41).reshape(-1)
     xt = to_gpu_c64(packed, dev)
     out = torch.empty_like(xt)
-    h = capi.fft_plan_many(list(sizes), capi.FFT_C64, capi.FFT_FORWARD)
+    h = capi.fft_plan_many_ex(list(sizes), capi.FFT_C64, capi.FFT_FORWARD, schedule)
     try:
         capi.fft_many_set_wait_limit(h, 1)
         capi.fft_exec(h, xt.data_ptr(), out.data_ptr(), torch.cuda.current_stream().cuda_stream)

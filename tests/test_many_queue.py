@@ -127,3 +127,85 @@ def test_queue_lag_interleaves():
     items0, _ = check_queue(sizes)
     first = [i for i, it in enumerate(items0) if it[0] == FIRST]
     assert first == list(range(len(first)))
+
+
+def simulate_ahead(items, first_tiles, workers, rng, ahead=1, static=True):
+    """The pipelined kernel's protocol: worker w runs items w, w + workers,
+    ... (static) or takes them from the queue `ahead` beyond the one it runs
+    (dynamic), in order; it releases a finished first-pass item only after
+    it has started its next item (or before any wait, or at exit), and a
+    second-pass item starts only after every first-pass item of its
+    transform is released."""
+    done = np.zeros(len(first_tiles), int)
+    head = 0
+    held = [[] for _ in range(workers)]     # items taken, in order
+    left = [None] * workers
+    pending = [None] * workers
+    steps = 0
+
+    nexts = list(range(workers))
+
+    def take(w):
+        nonlocal head
+        while len(held[w]) < 1 + ahead:
+            if static:
+                if nexts[w] >= len(items):
+                    return
+                held[w].append(items[nexts[w]])
+                nexts[w] += workers
+            else:
+                if head >= len(items):
+                    return
+                held[w].append(items[head])
+                head += 1
+
+    for w in range(workers):
+        take(w)
+    while any(held):
+        progressed = False
+        for w in range(workers):
+            if not held[w]:
+                if pending[w] is not None:
+                    done[pending[w]] += 1
+                    pending[w] = None
+                    progressed = True
+                continue
+            kind, _, a, _ = held[w][0]
+            if left[w] is None:
+                if kind == SECOND and done[a] < first_tiles[a]:
+                    if pending[w] is not None:   # release before waiting
+                        done[pending[w]] += 1
+                        pending[w] = None
+                        progressed = True
+                    continue
+                left[w] = int(rng.integers(1, 5))
+                if pending[w] is not None:       # released mid-way through the next item
+                    done[pending[w]] += 1
+                    pending[w] = None
+            left[w] -= 1
+            progressed = True
+            if left[w] == 0:
+                left[w] = None
+                held[w].pop(0)
+                if kind == FIRST:
+                    pending[w] = a
+                take(w)
+        assert progressed, "deadlock: every worker waits"
+        steps += 1
+    assert (done == first_tiles).all()
+    return steps
+
+
+@pytest.mark.parametrize("schedule", ["pipe=1;threads=512", "pipe=1;threads=512;pass2=1",
+                                      "pipe=1;threads=512;lag=2", "pipe=1;threads=512;order=given"])
+def test_queue_pipelined_protocol(schedule):
+    sizes = workloads.uneven_sizes(512, 8, 16, seed=3)
+    items, ft = check_queue(sizes, schedule)
+    for workers in (1, 2, 7, 256, 3000):
+        simulate_ahead(items, ft, workers, np.random.default_rng(workers))
+        simulate_ahead(items, ft, workers, np.random.default_rng(workers), ahead=2, static=False)
+    # uniform large transforms: every second-pass item depends on tiles taken
+    # by many workers
+    items, ft = check_queue([1 << 16] * 64, "pipe=1;threads=512")
+    for workers in (1, 3, 256):
+        simulate_ahead(items, ft, workers, np.random.default_rng(5 + workers))
