@@ -262,39 +262,42 @@ def tune_many(sizes, dtype=capi.FFT_C64, reps=10, verbose=False):
     total = int(sum(int(s) for s in sizes))
     esize = 8 if dtype == capi.FFT_C64 else 4
     bufs = _Buffers(total, esize, torch)
-    best = None
+
+    def timed(s):
+        try:
+            h = capi.fft_plan_many_ex(list(sizes), dtype, capi.FFT_FORWARD, s)
+        except capi.FFTError:
+            return None
+        try:
+            per, _ = _time_handle(h, bufs, reps)
+        finally:
+            capi.fft_destroy(h)
+        if verbose:
+            print(f"  {per[0]:9.2f} us  {s}", flush=True)
+        return per[0]
+
+    grid = []
     for P in (8, 16):
         for threads in (256, 512):
-            max_tile = min(12, int(math.log2(threads * P)))
-            for pass2 in range(max(8, max_tile - 3), max_tile + 2):
-                for order in ("bigfirst", "given"):
-                    s = f"p={P};threads={threads};pass2={pass2};order={order}"
-                    try:
-                        h = capi.fft_plan_many_ex(list(sizes), dtype, capi.FFT_FORWARD, s)
-                    except capi.FFTError:
-                        continue
-                    try:
-                        per, _ = _time_handle(h, bufs, reps)
-                    finally:
-                        capi.fft_destroy(h)
-                    if verbose:
-                        print(f"  {per[0]:9.2f} us  {s}", flush=True)
-                    if best is None or per[0] < best[0]:
-                        best = (per[0], s)
+            for pipe in (0, 1):
+                # the pipelined kernel keeps tiles up to 2^12 (512 lanes) or 2^11
+                max_tile = min(12 if (not pipe or threads == 512) else 11, int(math.log2(threads * P)))
+                for pass2 in range(max(8, max_tile - 3), max_tile + 2):
+                    for order in ("bigfirst", "given"):
+                        grid.append(f"p={P};threads={threads};pass2={pass2};order={order}"
+                                    + (";pipe=1" if pipe else ""))
+    best = None
+    for s in grid:
+        us = timed(s)
+        if us is not None and (best is None or us < best[0]):
+            best = (us, s)
     if best is not None:
         # queue order: second passes lagging the first passes by k transforms
         base = best[1]
         for lag in (1, 2, 4, 8):
-            s = f"{base};lag={lag}"
-            h = capi.fft_plan_many_ex(list(sizes), dtype, capi.FFT_FORWARD, s)
-            try:
-                per, _ = _time_handle(h, bufs, reps)
-            finally:
-                capi.fft_destroy(h)
-            if verbose:
-                print(f"  {per[0]:9.2f} us  {s}", flush=True)
-            if per[0] < best[0]:
-                best = (per[0], s)
+            us = timed(f"{base};lag={lag}")
+            if us is not None and us < best[0]:
+                best = (us, f"{base};lag={lag}")
     return best[1], [best[0]]
 
 

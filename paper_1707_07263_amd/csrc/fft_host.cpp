@@ -1104,7 +1104,7 @@ int build_many(const int64_t* sizes, int64_t count, int dtype, int direction, co
       mb->var = v;
   }
   if (!mb->var) return FFT_ERR_INVALID_ARGUMENT;
-  const int max_tile = std::min(kManyMaxLg, ilog2_64((int64_t)opt.threads * opt.P));
+  const int max_tile = std::min(mb->var->max_lg, ilog2_64((int64_t)opt.threads * opt.P));
   mb->max_tile = max_tile;
   if (opt.pass2 == 0) opt.pass2 = max_tile + 1;
   if (opt.pass2 < 1 || opt.pass2 > max_tile + 1) return FFT_ERR_INVALID_ARGUMENT;
@@ -1347,7 +1347,7 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
   if (var->pipe) {
     // the pipelined kernel's LDS image of the stage twiddles, gathered once
     std::vector<int32_t> map;
-    const int len = many_tw_image_map(a.stage_off, a.tw_used, opt.P, &map);
+    const int len = many_tw_image_map(a.stage_off, a.tw_used, opt.P, var->max_lg, &map);
     int32_t* d_map = nullptr;
     rc = upload((void**)&d_map, map.data(), map.size() * sizeof(int32_t));
     if (!rc) {

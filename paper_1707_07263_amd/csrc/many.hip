@@ -12,12 +12,12 @@ __host__ __device__ constexpr int many_lds_len(int lg) {
                  : (NT / ((1 << lg) / ((P < (1 << lg)) ? P : (1 << lg)))) *
                        ((1 << lg) + ((1 << lg) >> 4) + 1);
 }
-template <int P, int NT>
+template <int P, int NT, int MAXLG = kManyMaxLg>
 __host__ __device__ constexpr int many_lds_max(int lg = 0) {
-  return lg > kManyMaxLg ? 0
-                         : (many_lds_len<P, NT>(lg) > many_lds_max<P, NT>(lg + 1)
-                                ? many_lds_len<P, NT>(lg)
-                                : many_lds_max<P, NT>(lg + 1));
+  return lg > MAXLG ? 0
+                    : (many_lds_len<P, NT>(lg) > many_lds_max<P, NT, MAXLG>(lg + 1)
+                           ? many_lds_len<P, NT>(lg)
+                           : many_lds_max<P, NT, MAXLG>(lg + 1));
 }
 
 // One tile of length L (lines of L points, W = NT/T of them).
@@ -225,8 +225,8 @@ template <int P>
 struct ManyTwOff<P, 1> {
   static constexpr int value = 0;
 };
-template <int P>
-constexpr int many_tw_total() { return ManyTwOff<P, kManyMaxLg + 1>::value; }
+template <int P, int MAXLG = kManyMaxLg>
+constexpr int many_tw_total() { return ManyTwOff<P, MAXLG + 1>::value; }
 
 template <int P, int LG>
 void many_tw_map_lg(const int64_t* stage_off, int32_t tw_used, std::vector<int32_t>& map, int& len) {
@@ -245,9 +245,10 @@ void many_tw_map_lg(const int64_t* stage_off, int32_t tw_used, std::vector<int32
   }
 }
 
-int many_tw_image_map(const int64_t* stage_off, int32_t tw_used, int P, std::vector<int32_t>* map) {
+int many_tw_image_map(const int64_t* stage_off, int32_t tw_used, int P, int max_lg,
+                      std::vector<int32_t>* map) {
   if (P != 16) return 0;
-  map->assign(many_tw_total<16>(), -1);
+  map->assign(max_lg >= 12 ? many_tw_total<16, 12>() : many_tw_total<16, 11>(), -1);
   int len = 0;
   many_tw_map_lg<16, 1>(stage_off, tw_used, *map, len);
   return len;
@@ -422,11 +423,11 @@ __device__ __forceinline__ void many_body(const ManyArgs& a, const ManyItem& d, 
 // second-pass item's first pass (earlier in the queue) and releases its own
 // finished first-pass tiles before any wait, so the unfinished item of
 // lowest index always has its dependencies released and is being run.
-template <typename TS, int P, int NT>
+template <typename TS, int P, int NT, int MAXLG>
 __global__ void __launch_bounds__(NT, 1) k_many_pipe(ManyArgs a) {
-  static_assert(NT * P >= (1 << kManyMaxLg), "every tile length runs the barriers of `between`");
-  constexpr int XN = many_lds_max<P, NT>();
-  constexpr int TWN = many_tw_total<P>();
+  static_assert(NT * P >= (1 << MAXLG), "every tile length runs the barriers of `between`");
+  constexpr int XN = many_lds_max<P, NT, MAXLG>();
+  constexpr int TWN = many_tw_total<P, MAXLG>();
   __shared__ float2 lds[XN + TWN + 2 * NT];
   __shared__ int s_ready, s_last;
   float2* xch = lds;
@@ -552,16 +553,22 @@ __global__ void __launch_bounds__(NT, 1) k_many_pipe(ManyArgs a) {
       case 8: many_body<256, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 8>::value, rowl, tw_base, base, tid, between); break;
       case 9: many_body<512, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 9>::value, rowl, tw_base, base, tid, between); break;
       case 10:
-        if constexpr (NT * P >= 1024)
+        if constexpr (MAXLG >= 10)
           many_body<1024, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 10>::value, rowl, tw_base, base, tid, between);
+        else
+          between();
         break;
       case 11:
-        if constexpr (NT * P >= 2048)
+        if constexpr (MAXLG >= 11)
           many_body<2048, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 11>::value, rowl, tw_base, base, tid, between);
+        else
+          between();
         break;
       case 12:
-        if constexpr (NT * P >= 4096)
+        if constexpr (MAXLG >= 12)
           many_body<4096, P, NT, TS>(a, d, v, xch, twl + ManyTwOff<P, 12>::value, rowl, tw_base, base, tid, between);
+        else
+          between();
         break;
       default: between(); break;
     }
@@ -605,16 +612,17 @@ __global__ void __launch_bounds__(NT, 1) k_many_pipe(ManyArgs a) {
   }
 }
 
-template <typename TS, int P, int NT>
+template <typename TS, int P, int NT, int MAXLG>
 hipError_t launch_many_pipe(const ManyArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_many_pipe<TS, P, NT>), dim3(grid), dim3(NT), 0, s, a);
+  hipLaunchKernelGGL((k_many_pipe<TS, P, NT, MAXLG>), dim3(grid), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
-template <typename TS, int P, int NT>
+template <typename TS, int P, int NT, int MAXLG>
 int blocks_many_pipe() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_many_pipe<TS, P, NT>, NT, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_many_pipe<TS, P, NT, MAXLG>, NT, 0) != hipSuccess)
+    return 0;
   return n;
 }
 
@@ -631,15 +639,21 @@ int blocks_many() {
   return n;
 }
 
-#define MANY_VARIANT(TS, DT, P, NT) {DT, P, NT, 0, &launch_many<TS, P, NT>, &blocks_many<TS, P, NT>}
-#define MANY_PIPE(TS, DT, P, NT) {DT, P, NT, 1, &launch_many_pipe<TS, P, NT>, &blocks_many_pipe<TS, P, NT>}
+#define MANY_VARIANT(TS, DT, P, NT) \
+  {DT, P, NT, 0, kManyMaxLg, &launch_many<TS, P, NT>, &blocks_many<TS, P, NT>}
+// pipelined: 512 lanes (one workgroup per CU, tiles up to 2^12) or 256
+// lanes (two per CU, tiles up to 2^11 so that each fits half the LDS)
+#define MANY_PIPE(TS, DT, P, NT, MAXLG) \
+  {DT, P, NT, 1, MAXLG, &launch_many_pipe<TS, P, NT, MAXLG>, &blocks_many_pipe<TS, P, NT, MAXLG>}
 
 static const ManyVariant kManyVariants[] = {
     MANY_VARIANT(float2, DT_C64, 16, 256),   MANY_VARIANT(float2, DT_C64, 8, 256),
     MANY_VARIANT(float2, DT_C64, 16, 512),   MANY_VARIANT(__half2, DT_C16F, 16, 256),
     MANY_VARIANT(__half2, DT_C16F, 8, 256),  MANY_VARIANT(c16bf, DT_C16BF, 16, 256),
-    MANY_VARIANT(c16bf, DT_C16BF, 8, 256),   MANY_PIPE(float2, DT_C64, 16, 512),
-    MANY_PIPE(__half2, DT_C16F, 16, 512),    MANY_PIPE(c16bf, DT_C16BF, 16, 512),
+    MANY_VARIANT(c16bf, DT_C16BF, 8, 256),   MANY_PIPE(float2, DT_C64, 16, 512, 12),
+    MANY_PIPE(__half2, DT_C16F, 16, 512, 12),    MANY_PIPE(c16bf, DT_C16BF, 16, 512, 12),
+    MANY_PIPE(float2, DT_C64, 16, 256, 11),      MANY_PIPE(__half2, DT_C16F, 16, 256, 11),
+    MANY_PIPE(c16bf, DT_C16BF, 16, 256, 11),
 };
 
 int many_variant_count() { return (int)(sizeof(kManyVariants) / sizeof(kManyVariants[0])); }

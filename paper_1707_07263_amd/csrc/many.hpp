@@ -65,7 +65,8 @@ constexpr int kManyWsHeader = 4;  // ints before the per-transform counters
 
 struct ManyVariant {
   int dtype, P, threads;
-  int pipe;  // 1: software-pipelined, one workgroup per CU
+  int pipe;    // 1: software-pipelined
+  int max_lg;  // longest one-tile length, 2^max_lg
   hipError_t (*launch)(const ManyArgs&, int grid, hipStream_t);
   int (*max_blocks_per_cu)();
 };
@@ -74,7 +75,8 @@ struct ManyVariant {
 // entry i holds table element map[i] (an index into the plan's twiddle
 // table), or nothing (-1: row padding, unused lengths).  Returns the number
 // of entries the kernel copies (up to the longest used length).
-int many_tw_image_map(const int64_t* stage_off, int32_t tw_used, int P, std::vector<int32_t>* map);
+int many_tw_image_map(const int64_t* stage_off, int32_t tw_used, int P, int max_lg,
+                      std::vector<int32_t>* map);
 hipError_t launch_gather_f2(float2* dst, const float2* src, const int32_t* map, int n, hipStream_t s);
 
 // Compiled persistent-kernel variants (storage type x points per lane x

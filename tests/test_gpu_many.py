@@ -77,7 +77,7 @@ def test_uneven_512_complex64(dev, which):
     assert np.all(per_transform_errors(inv, ref_inv, sizes) <= tol)
 
 
-@pytest.mark.parametrize("pipe", [False, True])
+@pytest.mark.parametrize("pipe", [None, "pipe=1;threads=512", "pipe=1;threads=256"])
 @pytest.mark.parametrize("dt", ["f16", "bf16"])
 def test_uneven_512_16bit(dev, dt, pipe):
     code, tname = DT16[dt]
@@ -88,7 +88,7 @@ def test_uneven_512_16bit(dev, dt, pipe):
     out = torch.empty_like(xt)
     from paper_1707_07263_amd import autotune
     h = capi.fft_plan_many_ex(list(sizes), code, capi.FFT_FORWARD,
-                              "pipe=1;threads=512" if pipe else autotune.many_schedule_for(sizes, code))
+                              pipe if pipe else autotune.many_schedule_for(sizes, code))
     try:
         capi.fft_exec(h, xt.data_ptr(), out.data_ptr(), torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
@@ -107,7 +107,8 @@ def test_uneven_512_16bit(dev, dt, pipe):
 @pytest.mark.parametrize("schedule", [None, "p=8", "pass2=10", "pass2=13;order=given",
                                       "threads=512", "pass2=1", "lag=1", "lag=3;pass2=9",
                                       "pipe=1;threads=512", "pipe=1;threads=512;pass2=1",
-                                      "pipe=1;threads=512;pass2=9;lag=2"])
+                                      "pipe=1;threads=512;pass2=9;lag=2", "pipe=1;threads=256",
+                                      "pipe=1;threads=256;pass2=3"])
 def test_many_schedules_and_small_sizes(dev, schedule):
     # every length 2^0..2^16 twice, shuffled, under each compiled schedule
     g = workloads.rng(77)
@@ -122,7 +123,8 @@ def test_many_schedules_and_small_sizes(dev, schedule):
     assert np.all(errs <= tol), (schedule, float((errs / tol).max()))
 
 
-@pytest.mark.parametrize("schedule", ["lag=0", "lag=2", "threads=512;lag=1", "pipe=1;threads=512"])
+@pytest.mark.parametrize("schedule", ["lag=0", "lag=2", "threads=512;lag=1", "pipe=1;threads=512",
+                                      "pipe=1;threads=256"])
 def test_many_16x2p20_lagged_queue(dev, schedule):
     # sixteen 2^20-point transforms in one launch, second passes interleaved
     # with later first passes
@@ -157,7 +159,7 @@ def test_many_inverse_scale_and_repeat(dev):
         capi.fft_destroy(h)
 
 
-@pytest.mark.parametrize("schedule", [None, "pipe=1;threads=512"])
+@pytest.mark.parametrize("schedule", [None, "pipe=1;threads=512", "pipe=1;threads=256"])
 def test_many_graph_capture_replay(dev, schedule):
     sizes, packed = workloads.uneven_batch(128, 8, 16, seed=31)
     xt = to_gpu_c64(packed, dev)
@@ -190,7 +192,7 @@ def test_many_graph_capture_replay(dev, schedule):
         capi.fft_destroy(h)
 
 
-@pytest.mark.parametrize("schedule", [None, "pipe=1;threads=512"])
+@pytest.mark.parametrize("schedule", [None, "pipe=1;threads=512", "pipe=1;threads=256"])
 def test_many_bounded_wait_forced_from_host(dev, schedule):
     # A wait bound of 1 us makes a second-pass tile give up early when its
     # first-pass tiles are still running; the kernel must still finish, the

@@ -103,7 +103,8 @@ def test_queue_errors():
         with pytest.raises(capi.FFTError) as ei:
             capi.fft_describe_many(sizes)
         assert ei.value.status == code
-    for bad in ("p=7", "threads=100", "pass2=0", "pass2=14", "order=random", "x=1", "lag=-1"):
+    for bad in ("p=7", "threads=100", "pass2=0", "pass2=14", "order=random", "x=1", "lag=-1",
+                "pipe=1;threads=256;pass2=13", "pipe=2"):
         with pytest.raises(capi.FFTError) as ei:
             capi.fft_describe_many([256], schedule=bad)
         assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT, bad
@@ -197,7 +198,8 @@ def simulate_ahead(items, first_tiles, workers, rng, ahead=1, static=True):
 
 
 @pytest.mark.parametrize("schedule", ["pipe=1;threads=512", "pipe=1;threads=512;pass2=1",
-                                      "pipe=1;threads=512;lag=2", "pipe=1;threads=512;order=given"])
+                                      "pipe=1;threads=512;lag=2", "pipe=1;threads=512;order=given",
+                                      "pipe=1;threads=256", "pipe=1;threads=256;pass2=5"])
 def test_queue_pipelined_protocol(schedule):
     sizes = workloads.uneven_sizes(512, 8, 16, seed=3)
     items, ft = check_queue(sizes, schedule)
