@@ -22,6 +22,10 @@ Other modes (used to make the rocprofv3 summaries under profiles/):
   --mode profile     run warmup + steps only (no CPU baseline), for
                      `rocprofv3 --kernel-trace --stats` and `--pmc` runs;
                      also runs one plain 256 MiB device copy (calibration).
+  --mode configs     every benchmarked workload (1024 single, 1024 x 32768,
+                     16 x 2^20 forward and inverse, the 4096^2 image, the
+                     512 uneven batch in three storage types, 64 x 2^16
+                     forward + adjoint), one JSON line of per-workload rates
   --mode ablation    the method the paper improves on (Sec. 2.2: one global
                      radix-2 kernel per butterfly level) against the LDS
                      passes, forward 16 x 2^20, one JSON line
@@ -71,7 +75,7 @@ def parse_args(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--mode", choices=["bench", "profile", "ablation"], default="bench")
+    ap.add_argument("--mode", choices=["bench", "profile", "ablation", "configs"], default="bench")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--summarize-trace", metavar="DIR")
@@ -206,6 +210,89 @@ def cpu_baseline(x_np, seconds: float):
             "sample": f"{reps} x (forward + inverse of 16 x 2^20 complex, FP64 radix-2) in {el:.1f} s"}
 
 
+def _time_plans(capi, torch, plans, nbytes_io, reps):
+    """Average device time of running `plans` (each (handle, in/out element
+    count)) back to back, over rotating buffers of >= 1 GiB; per-launch HIP
+    events recorded by the library on the exec stream."""
+    stream = torch.cuda.current_stream().cuda_stream
+    # >= 1 GiB of rotating buffers (at most 64 sets: the latency-bound case
+    # is tiny and its working set stays cache-resident regardless)
+    nsets = min(64, max(2, math.ceil(ROT_BYTES / max(nbytes_io, 1))))
+    bufs = []
+    for _ in range(nsets):
+        bufs.append([(torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1),
+                      torch.empty(n, dtype=torch.uint8, device="cuda")) for _, n in plans])
+    for i in range(3):
+        for (h, _), (x, y) in zip(plans, bufs[i % nsets]):
+            capi.fft_exec(h, x.data_ptr(), y.data_ptr(), stream)
+    torch.cuda.synchronize()
+    for h, _ in plans:
+        capi.fft_profile_enable(h, reps)
+    for i in range(reps):
+        for (h, _), (x, y) in zip(plans, bufs[i % nsets]):
+            capi.fft_exec(h, x.data_ptr(), y.data_ptr(), stream)
+    torch.cuda.synchronize()
+    us = 0.0
+    for h, _ in plans:
+        capi.fft_profile_collect(h)
+        info = capi.fft_plan_info(h)
+        us += sum(1e3 * capi.fft_profile_read(h, p)[0] / reps for p in range(info["passes"]))
+        capi.fft_profile_enable(h, 0)
+    del bufs
+    torch.cuda.empty_cache()
+    return us
+
+
+def configs_report(capi, torch, reps):
+    """Rates of every benchmarked workload with its tuned schedule (inputs'
+    values do not change the timing; shapes and sizes are the workloads')."""
+    from paper_1707_07263_amd import autotune, workloads
+    out = {"mode": "configs", "reps": reps, "peak_GBps": PEAK_HBM_GBS, "configs": []}
+
+    def add(name, plans, dtype_bytes, note=""):
+        nbytes = sum(n for _, n in plans)
+        us = _time_plans(capi, torch, plans, 2 * nbytes, reps)
+        flops = sum(capi.fft_plan_info(h)["flops"] for h, _ in plans)
+        moved = sum(sum(capi.fft_plan_info(h)["bytes_pass"]) for h, _ in plans)
+        minimum = sum(capi.fft_plan_info(h)["bytes_min"] for h, _ in plans)
+        out["configs"].append({
+            "workload": name, "us": round(us, 2), "GFLOPs": round(flops / (us * 1e-6) / 1e9, 1),
+            "method_GBps": round(moved / (us * 1e-6) / 1e9, 1),
+            "method_frac": round(moved / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+            "min_GBps": round(minimum / (us * 1e-6) / 1e9, 1),
+            "schedules": [capi.fft_plan_info(h)["pass_variant"] for h, _ in plans], "note": note})
+        for h, _ in plans:
+            capi.fft_destroy(h)
+        print(f"[bench] {name}: {us:.2f} us", file=sys.stderr, flush=True)
+
+    def plan(shape, batch, dtype, direction, scale=None):
+        h = capi.fft_plan_ex(list(shape), batch, len(shape), dtype, direction,
+                             autotune.schedule_for(list(shape), batch, dtype))
+        if scale is not None:
+            capi.fft_set_scale(h, scale)
+        n = batch
+        for s_ in shape:
+            n *= s_
+        return h, n * (8 if dtype == capi.FFT_C64 else 4)
+
+    C64 = capi.FFT_C64
+    add("1-D N=1024 batch 1, forward (latency-bound)", [plan([1024], 1, C64, capi.FFT_FORWARD)], 8)
+    add("1-D N=1024 batch 32768, forward", [plan([1024], 32768, C64, capi.FFT_FORWARD)], 8)
+    add("1-D N=2^20 batch 16, forward then inverse",
+        [plan([N], BATCH, C64, capi.FFT_FORWARD), plan([N], BATCH, C64, capi.FFT_INVERSE)], 8)
+    add("2-D 4096x4096 image, forward", [plan([4096, 4096], 1, C64, capi.FFT_FORWARD)], 8)
+    add("1-D N=2^28 batch 1, forward (three passes, GPU FP64 twiddles)",
+        [plan([1 << 28], 1, C64, capi.FFT_FORWARD)], 8)
+    sizes = [int(v) for v in workloads.uneven_sizes(512, 8, 16, seed=3)]
+    for dt, name in ((C64, "complex64"), (capi.FFT_C16F, "fp16 pairs"), (capi.FFT_C16BF, "bf16 pairs")):
+        h = capi.fft_plan_many_ex(sizes, dt, capi.FFT_FORWARD, autotune.many_schedule_for(sizes, dt))
+        add(f"512 uneven 2^8..2^16 in one persistent launch, {name}", [(h, sum(sizes) * (8 if dt == C64 else 4))],
+            8 if dt == C64 else 4)
+    add("64 x 2^16 forward + adjoint backward (autograd pair)",
+        [plan([1 << 16], 64, C64, capi.FFT_FORWARD), plan([1 << 16], 64, C64, capi.FFT_INVERSE, 1.0)], 8)
+    return out
+
+
 def ablation(capi, torch, lds_plan, sets, nsets, stream, reps):
     """Forward 16 x 2^20 with the LDS passes and with one radix-2 kernel per
     level (log2 N = 20 launches, each moving every point), timed alike."""
@@ -292,6 +379,11 @@ def main(argv=None) -> int:
 
     if args.mode == "ablation":
         print(json.dumps(ablation(capi, torch, fwd, sets, nsets, stream, args.steps)))
+        return 0
+    if args.mode == "configs":
+        del sets
+        torch.cuda.empty_cache()
+        print(json.dumps(configs_report(capi, torch, args.steps)))
         return 0
 
     if args.mode == "profile":

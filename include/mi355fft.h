@@ -67,8 +67,9 @@ typedef struct fft_plan_s *fft_plan_t;
 #define FFT_ERR_NO_MEMORY (-6)        /* host or device allocation failed */
 #define FFT_ERR_WATCHDOG (-7)         /* the batched kernel's bounded wait expired */
 
-/* Size limits.  1-D lengths 1 .. 2^24; 2-D extents 1 .. 2^14 each. */
-#define FFT_MAX_LOG2_1D 24
+/* Size limits.  1-D lengths 1 .. 2^28 (three passes above 2^24); 2-D
+ * extents 1 .. 2^14 each.  Batched plans (fft_plan_many*) take 1 .. 2^24. */
+#define FFT_MAX_LOG2_1D 28
 #define FFT_MAX_LOG2_2D 14
 
 /*
@@ -86,7 +87,11 @@ int fft_plan(const int64_t *n, int64_t batch, int dims, int dtype, int direction
  * As fft_plan, with an explicit schedule string (used by the autotuner and
  * by tests).  NULL or "" selects the built-in choice.  Grammar:
  *   schedule := item (';' item)*
- *   item     := 'split=' N1            (1-D two-pass: first-pass length)
+ *   item     := 'split=' N1            (1-D two-pass: first-pass length; three-pass:
+ *                                       first-pass length, default 2^10)
+ *             | 'split2=' N2          (1-D three-pass (Sec. 2.3.3's "cube": N =
+ *                                       N1*N2*N3, used above 2^24 or when given):
+ *                                       second-pass length, 2 .. 2^7, default 2^7)
  *             | 'a=' variant | 'b=' variant | 'row=' variant | 'col=' variant
  *             | 'single=' variant
  *             | 'xcd=' digits         (one '0'/'1' for every pass, or one digit
@@ -176,8 +181,8 @@ int fft_many_set_wait_limit(fft_plan_t plan, int64_t microseconds);
  * Queue the transform on `stream`.  Asynchronous: no host synchronisation, no
  * allocation, no host reads of device data, so it may be captured into a
  * hipGraph.  `in` and `out` must not partially overlap; in == out is allowed
- * for one-pass plans, and for multi-pass plans once a workspace of
- * fft_workspace_size() bytes is set (else FFT_ERR_INPLACE).  Input data are
+ * for one-pass plans, for three-pass plans, and for two-pass plans once a
+ * workspace of fft_workspace_size() bytes is set (else FFT_ERR_INPLACE).  Input data are
  * not modified unless in == out.
  */
 int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
@@ -190,11 +195,12 @@ int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
 int fft_set_scale(fft_plan_t plan, double scale);
 
 /*
- * Device scratch a plan needs to run in place (1-D two-pass) or, for
- * plan_many, for its queue and counters.  fft_set_workspace hands the plan
- * caller-owned device memory of at least that many bytes (NULL, 0 returns to
- * the plan-owned default, if any); the caller keeps it alive while the plan
- * may run.
+ * Device scratch a plan needs to run in place (1-D two-pass), on every exec
+ * (1-D three-pass plans, lengths above 2^24: one buffer of batch * N
+ * elements, allocated by the plan) or, for plan_many, for its queue and
+ * counters.  fft_set_workspace hands the plan caller-owned device memory of
+ * at least that many bytes (NULL, 0 returns to the plan-owned default, if
+ * any); the caller keeps it alive while the plan may run.
  */
 int fft_workspace_size(fft_plan_t plan, size_t *bytes);
 int fft_set_workspace(fft_plan_t plan, void *ptr, size_t bytes);

@@ -44,9 +44,11 @@ def _declare(lib):
     lib.oracle_fft2d.argtypes = [dp, i64, i64, i64, ctypes.c_int, ctypes.c_double]
     lib.oracle_fft_many.argtypes = [dp, ctypes.POINTER(i64), i64, ctypes.c_int, ctypes.c_double]
     lib.oracle_dft_direct.argtypes = [dp, dp, i64, ctypes.c_int]
+    lib.oracle_dft_at.argtypes = [dp, i64, ctypes.POINTER(i64), i64, ctypes.c_int, ctypes.c_double, dp]
     lib.oracle_max_threads.restype = ctypes.c_int
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
-    for f in (lib.oracle_fft1d, lib.oracle_fft2d, lib.oracle_fft_many, lib.oracle_dft_direct):
+    for f in (lib.oracle_fft1d, lib.oracle_fft2d, lib.oracle_fft_many, lib.oracle_dft_direct,
+              lib.oracle_dft_at):
         f.restype = ctypes.c_int
     return lib
 
@@ -122,6 +124,20 @@ def fft_many(packed, sizes, inverse: bool = False, scale: float | None = None) -
     return a
 
 
+def dft_at(x, ks, inverse: bool = False, scale: float | None = None) -> np.ndarray:
+    """Selected outputs X[ks] of one transform of x (1-D, length a power of
+    two), each summed term by term in long double; O(N) per output."""
+    a = _as_c128(x)
+    if a.ndim != 1:
+        raise ValueError("dft_at takes one transform")
+    ks = np.ascontiguousarray(np.asarray(ks, dtype=np.int64))
+    out = np.empty(len(ks), dtype=np.complex128)
+    _check(_load().oracle_dft_at(_ptr(a), a.shape[0], ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 len(ks), _sign(inverse), -1.0 if scale is None else float(scale),
+                                 _ptr(out)), "dft_at")
+    return out
+
+
 def dft_direct(x, inverse: bool = False) -> np.ndarray:
     """Eq. 1 / eq. 2 term by term in long double (any N >= 1, O(N^2))."""
     a = _as_c128(x)
@@ -180,3 +196,6 @@ class Oracle:
 
     def dft_direct(self, *a, **k):
         return self._swap(dft_direct, *a, **k)
+
+    def dft_at(self, *a, **k):
+        return self._swap(dft_at, *a, **k)

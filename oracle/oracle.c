@@ -25,6 +25,9 @@
  *   oracle_dft_direct - eq. 1 / eq. 2 evaluated term by term in long double,
  *                    with the exponent n*k reduced mod N first (periodicity,
  *                    eq. 3); used to check oracle_fft1d on small N.
+ *   oracle_dft_at  - the same sum for a few selected outputs k of a long
+ *                    transform (O(N) each), for checking results the full
+ *                    oracle is too slow or too large for.
  *   oracle_fft2d   - 1-D transforms of every row, then of every column
  *                    (rows first, then columns: Sec. 2.3.2).
  *   oracle_fft_many - independent 1-D transforms packed back to back.
@@ -262,6 +265,72 @@ int oracle_dft_direct(const double *in, double *out, int64_t n, int sign) {
 }
 
 /* Threads an OpenMP parallel region of this library would use. */
+/*
+ * Outputs X[ks[i]] of eq. 1 (sign -1) or eq. 2 (sign +1), each
+ * sum_t x[t] W_N^{sign * t k}, times `scale` (negative: 1 forward, 1/N
+ * inverse), in long double.  The exponent t*k is reduced mod N exactly; with
+ * t = a*S + b (S = 2^ceil(log2(N)/2)) the factor W_N^{tk} is the product of
+ * W_N^{(a S k) mod N} and W_N^{(b k) mod N}, each from cosl/sinl of an
+ * exact ratio, so the sum costs one complex multiply-add per term.  N must
+ * be a power of two.
+ */
+int oracle_dft_at(const double *in, int64_t n, const int64_t *ks, int64_t nk, int sign,
+                  double scale, double *out) {
+  if (!in || !ks || !out || n < 1 || nk < 0 || !check_dir(sign)) return -1;
+  if (!is_pow2(n)) return -2;
+  const int m = log2_exact(n);
+  const int64_t S = (int64_t)1 << ((m + 1) / 2);
+  const int64_t A = n / S < 1 ? 1 : n / S;
+  const int64_t Sb = n < S ? n : S;
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  const long double sc = scale < 0.0 ? (long double)default_scale(n, sign) : (long double)scale;
+  int fail = 0;
+#pragma omp parallel
+  {
+    long double *ta = (long double *)malloc((size_t)A * 2 * sizeof(long double));
+    long double *tb = (long double *)malloc((size_t)Sb * 2 * sizeof(long double));
+    if (!ta || !tb) {
+#pragma omp atomic write
+      fail = 1;
+    }
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t i = 0; i < nk; ++i) {
+      if (!ta || !tb) continue;
+      const int64_t k = ((ks[i] % n) + n) % n;
+      for (int64_t a = 0; a < A; ++a) {
+        const int64_t e = (int64_t)(((unsigned __int128)(a * Sb) * (unsigned __int128)k) %
+                                    (unsigned __int128)n);
+        const long double ang = two_pi * (long double)e / (long double)n;
+        ta[2 * a] = cosl(ang);
+        ta[2 * a + 1] = (long double)sign * sinl(ang);
+      }
+      for (int64_t b = 0; b < Sb; ++b) {
+        const int64_t e = (int64_t)(((unsigned __int128)b * (unsigned __int128)k) % (unsigned __int128)n);
+        const long double ang = two_pi * (long double)e / (long double)n;
+        tb[2 * b] = cosl(ang);
+        tb[2 * b + 1] = (long double)sign * sinl(ang);
+      }
+      long double sr = 0.0L, si = 0.0L;
+      for (int64_t a = 0; a < A; ++a) {
+        long double pr = 0.0L, pi = 0.0L;
+        const double *xa = in + 2 * a * Sb;
+        for (int64_t b = 0; b < Sb; ++b) {
+          const long double xr = xa[2 * b], xi = xa[2 * b + 1];
+          pr += xr * tb[2 * b] - xi * tb[2 * b + 1];
+          pi += xr * tb[2 * b + 1] + xi * tb[2 * b];
+        }
+        sr += pr * ta[2 * a] - pi * ta[2 * a + 1];
+        si += pr * ta[2 * a + 1] + pi * ta[2 * a];
+      }
+      out[2 * i] = (double)(sr * sc);
+      out[2 * i + 1] = (double)(si * sc);
+    }
+    free(ta);
+    free(tb);
+  }
+  return fail ? -6 : 0;
+}
+
 int oracle_max_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -107,6 +107,9 @@ struct PassSpec {
   int64_t tw_N = 0;            // inter-pass twiddle modulus (0: none)
   int64_t tw_rows = 0;         // rows of its step table
   std::vector<int32_t> line_map;  // row pass of the three-pass 2-D plan
+  // launched once per transform of the batch, pointers advanced by the
+  // transform's length (the last pass of the three-pass 1-D plan)
+  bool per_transform = false;
 };
 
 struct Schedule {
@@ -114,6 +117,9 @@ struct Schedule {
   int64_t split[2] = {0, 0};
   int64_t points = 0;
   bool inplace_needs_ws = false;
+  // every exec needs a workspace of `points` elements (passes read or write
+  // SEL_WS); the plan allocates one unless the caller sets its own
+  bool always_ws = false;
   // one global-memory kernel per radix-2 level instead of LDS passes
   bool levels = false;
 };
@@ -124,6 +130,7 @@ struct Overrides {
   // every pass; otherwise one digit per pass, first pass first.
   std::string xcd = "0";
   int col3 = -1;  // 2-D columns in two sub-passes: 1 yes, 0 no, -1 automatic
+  int64_t split2 = 0;  // three-pass 1-D: second-pass length
   bool levels = false;  // method=levels: the per-level global-memory method
   std::string a, b, row, col, single, colt;
 };
@@ -146,6 +153,11 @@ int parse_schedule(const char* s, Overrides* o) {
       long long v = strtoll(val.c_str(), &e, 10);
       if (!e || *e || v < 1) return FFT_ERR_INVALID_ARGUMENT;
       o->split = v;
+    } else if (key == "split2") {
+      char* e = nullptr;
+      long long v = strtoll(val.c_str(), &e, 10);
+      if (!e || *e || v < 2) return FFT_ERR_INVALID_ARGUMENT;
+      o->split2 = v;
     } else if (key == "xcd") {
       if (val.empty() || val.size() > 4 || val.find_first_not_of("01") != std::string::npos)
         return FFT_ERR_INVALID_ARGUMENT;
@@ -182,6 +194,90 @@ int choose(const std::string& name, int role, int L, int dtype, int want_w, int6
 
 constexpr int kSingleMaxLog2 = 14;  // one-kernel transforms up to 2^14 points
 constexpr int kSplitMinLog2 = 6, kSplitMaxLog2 = 12;
+
+// 1-D lengths beyond two passes of 2^12: N = N1*N2*N3 in three passes, the
+// four-step identity applied twice.  With n = N2*N3*n1 + N3*n2 + n3 and
+// k = k1 + N1*k2 + N1*N2*k3, W_N^{nk} factors as
+//   W_N1^{n1 k1} * W_N^{m k1} (m = N3 n2 + n3) * W_N2^{n2 k2} * W_M^{n3 k2} * W_N3^{n3 k3}
+// with M = N2*N3, so
+//   pass 1: N1-point columns of x viewed as [N1][M], times W_N^{m k1},
+//           stored transposed as T1[m*N1 + k1]           (in -> workspace)
+//   pass 2: N2-point columns (line n3*N1 + k1, stride N3*N1), times
+//           W_M^{n3 k2}, in place                          (workspace)
+//   pass 3: N3-point columns (line k1 of block k2, stride N1), stored at
+//           X[k1 + N1 k2 + N1 N2 k3]                       (workspace -> out)
+int build_three_pass_1d(int64_t N, int64_t batch, int dtype, const Overrides& ov, Schedule* outp) {
+  Schedule& S = *outp;
+  const int l = ilog2_64(N);
+  const int l1 = ov.split ? ilog2_64(ov.split) : 10;
+  const int l2 = ov.split2 ? ilog2_64(ov.split2) : 7;
+  const int l3 = l - l1 - l2;
+  if ((ov.split && !pow2(ov.split)) || (ov.split2 && !pow2(ov.split2))) return FFT_ERR_INVALID_ARGUMENT;
+  if (l1 < 1 || l2 < 1 || l3 < 1 || l1 > kSplitMaxLog2 || l2 > 7 || l3 > kSingleMaxLog2)
+    return FFT_ERR_INVALID_ARGUMENT;
+  const int64_t N1 = (int64_t)1 << l1, N2 = (int64_t)1 << l2, N3 = (int64_t)1 << l3;
+  const int64_t M = N2 * N3;
+  PassSpec A, C, B;
+  int rc = choose(ov.a, ROLE_SPLIT_A, (int)N1, dtype, 16, M, &A.v);
+  if (rc) return rc;
+  rc = choose(ov.colt, ROLE_COL_TW, (int)N2, dtype, 64, N3 * N1, &C.v);
+  if (rc) return rc;
+  rc = choose(ov.b.empty() ? ov.col : ov.b, ROLE_COL, (int)N3, dtype, 16, N1, &B.v);
+  if (rc) return rc;
+  if (M > INT32_MAX || N3 * N1 > INT32_MAX) return FFT_ERR_UNSUPPORTED_SIZE;
+  PassArgs& a = A.args;
+  a.in_batch = a.out_batch = N;
+  a.in_line = 1;
+  a.in_elem = M;
+  a.out_line = N1;
+  a.out_elem = 1;
+  a.lines = (int32_t)M;
+  a.tiles_per_batch = (int32_t)((M + A.v->W - 1) / A.v->W);
+  a.total_tiles = (int64_t)a.tiles_per_batch * batch;
+  a.tw_shift = (l + 1) / 2;
+  a.tw_mask = (1 << a.tw_shift) - 1;
+  A.tw_N = N;
+  A.tw_rows = M;
+  A.src = SEL_IN;
+  A.dst = SEL_WS;
+  A.first = true;
+  PassArgs& c = C.args;
+  c.in_batch = c.out_batch = N;
+  c.in_line = c.out_line = 1;
+  c.in_elem = c.out_elem = N3 * N1;
+  c.lines = (int32_t)(N3 * N1);
+  c.tiles_per_batch = (int32_t)(N3 * N1 / C.v->W);
+  c.total_tiles = (int64_t)c.tiles_per_batch * batch;
+  c.tw_shift = (l2 + l3 + 1) / 2;
+  c.tw_mask = (1 << c.tw_shift) - 1;
+  c.tw_line_shift = l1;
+  C.tw_N = M;
+  C.tw_rows = N3;
+  C.src = SEL_WS;
+  C.dst = SEL_WS;
+  PassArgs& b = B.args;
+  b.in_batch = N3 * N1;  // block k2
+  b.out_batch = N1;
+  b.in_line = b.out_line = 1;
+  b.in_elem = N1;
+  b.out_elem = N1 * N2;
+  b.lines = (int32_t)N1;
+  b.tiles_per_batch = (int32_t)((N1 + B.v->W - 1) / B.v->W);
+  b.total_tiles = (int64_t)b.tiles_per_batch * N2;  // one transform; launched per transform
+  B.per_transform = true;
+  B.src = SEL_WS;
+  B.dst = SEL_OUT;
+  B.last = true;
+  if (C.v->W > N3 * N1 || a.total_tiles > INT32_MAX || c.total_tiles > INT32_MAX || b.total_tiles > INT32_MAX)
+    return FFT_ERR_UNSUPPORTED_SIZE;
+  S.split[0] = N1;
+  S.split[1] = M;
+  S.always_ws = true;
+  S.passes.push_back(A);
+  S.passes.push_back(C);
+  S.passes.push_back(B);
+  return FFT_OK;
+}
 
 // Columns of length R = Sq*Sq as two in-place column passes (the
 // three-exchange decomposition: the image viewed as [Sq][Sq][C]), then the
@@ -270,6 +366,12 @@ int build_schedule_inner(const int64_t* n, int64_t batch, int dims, int dtype, c
     const int l = ilog2_64(N);
     if (ov.levels && N > 1) {
       S.levels = true;
+      *out = S;
+      return FFT_OK;
+    }
+    if (l > 2 * kSplitMaxLog2 || ov.split2) {
+      int rc = build_three_pass_1d(N, batch, dtype, ov, &S);
+      if (rc) return rc;
       *out = S;
       return FFT_OK;
     }
@@ -753,6 +855,18 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
     return hip_fail(e);
   }
   p->cus = cus;
+  if (S.always_ws) {
+    // plan-owned workspace (the caller may replace it with fft_set_workspace)
+    const size_t bytes = (size_t)S.points * esize(dtype);
+    e = hipMalloc(&p->ws, bytes);
+    if (e != hipSuccess) {
+      p->ws = nullptr;
+      fft_destroy(p);
+      return e == hipErrorOutOfMemory ? FFT_ERR_NO_MEMORY : hip_fail(e);
+    }
+    p->ws_bytes = bytes;
+    p->ws_owned = true;
+  }
   if (S.levels) {
     e = hipMalloc(&p->lv_buf, (size_t)S.points * esize(dtype));
     if (e != hipSuccess) {
@@ -808,7 +922,7 @@ int fft_set_scale(fft_plan_t p, double scale) {
 int fft_workspace_size(fft_plan_t p, size_t* bytes) {
   if (!p || !bytes) return FFT_ERR_INVALID_ARGUMENT;
   if (p->kind == 1) *bytes = many_workspace_bytes(p->many);
-  else *bytes = p->sched.inplace_needs_ws ? (size_t)p->sched.points * esize(p->dtype) : 0;
+  else *bytes = (p->sched.inplace_needs_ws || p->sched.always_ws) ? (size_t)p->sched.points * esize(p->dtype) : 0;
   return FFT_OK;
 }
 
@@ -824,7 +938,16 @@ int fft_set_workspace(fft_plan_t p, void* ptr, size_t bytes) {
   p->ws_owned = false;
   p->ws = ptr;
   p->ws_bytes = ptr ? bytes : 0;
-  if (!ptr && p->kind == 1) {
+  if (!ptr && p->kind == 0 && p->sched.always_ws) {
+    // back to a plan-owned workspace
+    hipError_t e = hipMalloc(&p->ws, need);
+    if (e != hipSuccess) {
+      p->ws = nullptr;
+      return e == hipErrorOutOfMemory ? FFT_ERR_NO_MEMORY : hip_fail(e);
+    }
+    p->ws_bytes = need;
+    p->ws_owned = true;
+  } else if (!ptr && p->kind == 1) {
     // back to a plan-owned queue workspace
     int rc = many_alloc_workspace(p->many, &p->ws, &p->ws_bytes);
     if (rc) return rc == FFT_ERR_HIP ? hip_fail((hipError_t)g_last_hip) : rc;
@@ -883,14 +1006,23 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
     if (!p->ws) return FFT_ERR_INPLACE;
     ws = p->ws;
   }
+  if (S.always_ws && !p->ws) return FFT_ERR_INPLACE;
   const bool inv = p->direction > 0;
   hipEvent_t* slot = prof_slot(p);
   for (size_t i = 0; i < S.passes.size(); ++i) {
     const PassSpec& ps = S.passes[i];
     // out of place: each pass reads `in` (first) or `out` and writes `out`;
-    // in place with a workspace: A reads in and writes ws, B reads ws, writes out
-    void* src = ws ? (i == 0 ? (void*)in : ws) : (ps.src == SEL_IN ? (void*)in : out);
-    void* dst = ws ? (i == 0 ? ws : out) : out;
+    // in place with a workspace: A reads in and writes ws, B reads ws, writes out;
+    // plans that always use the workspace name their buffers per pass
+    void* src;
+    void* dst;
+    if (S.always_ws) {
+      src = ps.src == SEL_IN ? (void*)in : ps.src == SEL_WS ? p->ws : out;
+      dst = ps.dst == SEL_IN ? (void*)in : ps.dst == SEL_WS ? p->ws : out;
+    } else {
+      src = ws ? (i == 0 ? (void*)in : ws) : (ps.src == SEL_IN ? (void*)in : out);
+      dst = ws ? (i == 0 ? ws : out) : out;
+    }
     if (slot) hipEventRecord(slot[2 * i], s);
     hipError_t e;
     if (!ps.v) {
@@ -906,7 +1038,17 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
                               : (inv ? 1.0f / (float)ps.v->L : 1.0f);
       a.conj_in = (inv && ps.first) ? 1 : 0;
       a.conj_out = (inv && ps.last) ? 1 : 0;
-      e = ps.v->launch(a, s);
+      if (ps.per_transform && p->batch > 1) {
+        const size_t step = (size_t)(S.points / p->batch) * esize(p->dtype);
+        e = hipSuccess;
+        for (int64_t b = 0; b < p->batch && e == hipSuccess; ++b) {
+          a.in = (const char*)src + b * step;
+          a.out = (char*)dst + b * step;
+          e = ps.v->launch(a, s);
+        }
+      } else {
+        e = ps.v->launch(a, s);
+      }
     }
     if (slot) hipEventRecord(slot[2 * i + 1], s);
     if (e != hipSuccess) return hip_fail(e);

@@ -93,7 +93,7 @@ def test_describe_schedule_overrides(lib):
 @pytest.mark.parametrize("n,dims,dtype,code", [
     ([12], 1, 0, capi.FFT_ERR_UNSUPPORTED_SIZE),
     ([0], 1, 0, capi.FFT_ERR_UNSUPPORTED_SIZE),
-    ([1 << 25], 1, 0, capi.FFT_ERR_UNSUPPORTED_SIZE),
+    ([1 << 29], 1, 0, capi.FFT_ERR_UNSUPPORTED_SIZE),
     ([1 << 15, 4], 2, 0, capi.FFT_ERR_UNSUPPORTED_SIZE),
     ([16], 3, 0, capi.FFT_ERR_INVALID_ARGUMENT),
     ([16], 1, 9, capi.FFT_ERR_INVALID_ARGUMENT),
@@ -193,3 +193,22 @@ def test_describe_xcd_masks(lib):
     for bad in ("xcd=011", "xcd=2", "xcd=", "xcd=00000"):
         with pytest.raises(capi.FFTError):
             capi.fft_describe([1 << 20], 16, 1, capi.FFT_C64, bad)
+
+
+
+def test_describe_three_pass_1d(lib):
+    # beyond two passes of 2^12: N1 x N2 x N3 = 2^10 x 2^7 x 2^(l-17)
+    for l in (25, 26, 27, 28):
+        d = capi.fft_describe([1 << l], 1, 1, capi.FFT_C64)
+        assert d["passes"] == 3 and d["split"] == [1024, 1 << (l - 10)]
+        assert d["names"][0].startswith("a1024p") and d["names"][1].startswith("t128p")
+        assert d["names"][2].startswith(f"c{1 << (l - 17)}p")
+    # forced at smaller sizes
+    for n, sched in ((1 << 12, "split=64;split2=16"), (1 << 16, "split=256;split2=8"),
+                     (1 << 20, "split=1024;split2=128"), (1 << 18, "split=64;split2=2")):
+        assert capi.fft_describe([n], 3, 1, capi.FFT_C64, sched)["passes"] == 3
+    d = capi.fft_describe([1 << 16], 3, 1, capi.FFT_C64, "split=256;split2=8")
+    assert d["passes"] == 3 and d["names"][1].startswith("t8p") and d["names"][2].startswith("c32p")
+    for bad in ("split2=256", "split=8192;split2=4", "split2=3", "split2=65536"):
+        with pytest.raises(capi.FFTError):
+            capi.fft_describe([1 << 26], 1, 1, capi.FFT_C64, bad)

@@ -396,3 +396,63 @@ def test_column_twiddle_variants(dev, name):
     got = run_c64(x, [r, c], schedule=sched, dev=dev)
     ref = oracle.fft2(x.astype(np.complex64))
     assert rel_l2_rows(got.reshape(2, -1), ref.reshape(2, -1), r * c).max() <= tol_fp32(r * c)
+
+
+THREE_PASS_1D = [(1 << 12, "split=64;split2=16"), (1 << 16, "split=256;split2=8"),
+                 (1 << 20, "split=1024;split2=128"), (1 << 18, "split=64;split2=2")]
+
+
+@pytest.mark.parametrize("n,sched", THREE_PASS_1D)
+@pytest.mark.parametrize("inverse", [False, True])
+def test_three_pass_1d_forced(dev, n, sched, inverse):
+    # N1 x N2 x N3 with a ragged batch of 3 (the last pass runs per transform)
+    x = workloads.normal_batch(n, 3, seed=n % 9973)
+    check_1d(x, n, inverse, dev, schedule=sched)
+    got = run_c64(x, [n], inverse=inverse, schedule=sched, inplace=True, dev=dev)
+    ref = oracle.fft(np.asarray(x, np.complex64), inverse=inverse)
+    assert rel_l2_rows(got, ref, n).max() <= tol_fp32(n)
+
+
+def test_three_pass_1d_2p25_full(dev):
+    n = 1 << 25
+    x = workloads.normal_batch(n, 1, seed=25).astype(np.complex64)
+    assert capi.fft_describe([n], 1, 1, capi.FFT_C64)["passes"] == 3
+    got = run_c64(x, [n], dev=dev)
+    err = rel_l2_rows(got, oracle.fft(x), n)
+    print(f"2^25 three-pass rel-L2 {err.max():.3e}")
+    assert err.max() <= tol_fp32(n)
+
+
+def test_three_pass_1d_2p28_sampled(dev):
+    # 2^28 points: outputs sampled against the long-double sum, the round
+    # trip and Parseval over the whole array
+    n = 1 << 28
+    g = np.random.default_rng(28)
+    x = (g.standard_normal(n, dtype=np.float32) + 1j * g.standard_normal(n, dtype=np.float32)).astype(np.complex64)
+    xt = to_gpu_c64(x, dev)
+    fwd = capi.fft_plan([n], 1, 1, capi.FFT_C64, capi.FFT_FORWARD)
+    inv = capi.fft_plan([n], 1, 1, capi.FFT_C64, capi.FFT_INVERSE)
+    try:
+        assert capi.fft_plan_info(fwd)["gpu_twiddles"] == 1
+        y = torch.empty_like(xt)
+        z = torch.empty_like(xt)
+        st = torch.cuda.current_stream().cuda_stream
+        capi.fft_exec(fwd, xt.data_ptr(), y.data_ptr(), st)
+        capi.fft_exec(inv, y.data_ptr(), z.data_ptr(), st)
+        torch.cuda.synchronize()
+        rt = (torch.linalg.vector_norm(z - xt) / torch.linalg.vector_norm(xt)).item()
+        ex = torch.linalg.vector_norm(xt.to(torch.complex128)).item() ** 2
+        ey = torch.linalg.vector_norm(y.to(torch.complex128)).item() ** 2 / n
+        ks = np.array([0, 1, 2, 12345, (1 << 27) + 3, n - 1, 98765432, 3 * (n // 4)])
+        ys = y[torch.from_numpy(ks).to(dev)].cpu().numpy()
+    finally:
+        capi.fft_destroy(fwd)
+        capi.fft_destroy(inv)
+    del xt, y, z
+    ref = oracle.dft_at(x, ks)
+    rms = math.sqrt(n * 2.0)  # |X[k]| scale for unit-variance complex input
+    worst = float(np.max(np.abs(ys - ref)) / rms)
+    print(f"2^28: sampled |err|/rms {worst:.3e}, round trip {rt:.3e}, Parseval {abs(ey - ex) / ex:.3e}")
+    assert worst <= tol_fp32(n)
+    assert rt <= 2 * tol_fp32(n)
+    assert abs(ey - ex) / ex <= 1e-5

@@ -270,3 +270,44 @@ def test_thread_count_does_not_change_results(oracle_mod):
     finally:
         oracle_mod.set_threads(prev)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("m", [0, 1, 3, 7, 10])
+def test_sampled_outputs_vs_brute_force(oracle_mod, m):
+    # every output of a small transform, both directions
+    n = 1 << m
+    x = workloads.normal_batch(n, 1, seed=900 + m)[0]
+    ks = np.arange(n)
+    assert rel_l2(oracle_mod.dft_at(x, ks), brute_dft(x, -1)) < 1e-15 * max(1, m) + 1e-16
+    assert rel_l2(oracle_mod.dft_at(x, ks, inverse=True), brute_dft(x, +1) / n) < 1e-15 * max(1, m) + 1e-16
+    # scale override, and indices taken mod N (periodicity, eq. 3)
+    assert rel_l2(oracle_mod.dft_at(x, ks, inverse=True, scale=1.0), brute_dft(x, +1)) < 1e-15 * max(1, m) + 1e-16
+    wrap = oracle_mod.dft_at(x, ks + 3 * n)
+    assert rel_l2(wrap, oracle_mod.dft_at(x, ks)) == 0.0
+
+
+def test_sampled_outputs_long_transforms(oracle_mod):
+    # closed forms at 2^22: impulse at n0 -> W_N^{n0 k}; tone k0 -> N at k0
+    n = 1 << 22
+    ks = np.array([0, 1, 5, 12345, n // 2, n - 1, 3 * n // 4 + 7])
+    x = np.zeros(n, complex)
+    n0 = 987654
+    x[n0] = 1.0
+    want = np.exp(-2j * np.pi * ((n0 * ks) % n) / n)
+    assert np.max(np.abs(oracle_mod.dft_at(x, ks) - want)) < 1e-15
+    k0 = 123457
+    t = np.arange(n)
+    tone = np.exp(2j * np.pi * ((k0 * t) % n) / n)
+    got = oracle_mod.dft_at(tone, [k0, k0 + 1, 0])
+    assert abs(got[0] - n) < 1e-9 * n and np.max(np.abs(got[1:])) < 1e-9 * n
+    # random input at 2^16: agrees with the radix-2 oracle at sampled outputs
+    y = workloads.normal_batch(1 << 16, 1, seed=5)[0]
+    ks = np.array([0, 3, 777, 32768, 65535])
+    assert rel_l2(oracle_mod.dft_at(y, ks), oracle_mod.fft(y)[ks]) < 1e-14
+
+
+def test_sampled_outputs_errors(oracle_mod):
+    with pytest.raises(ValueError):
+        oracle_mod.dft_at(np.zeros(12, complex), [0])
+    with pytest.raises(ValueError):
+        oracle_mod.dft_at(np.zeros((2, 4), complex), [0])

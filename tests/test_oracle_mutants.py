@@ -30,6 +30,9 @@ MUTANTS = {
     "packed_first_scale": ("default_scale(sizes[i], sign)", "default_scale(sizes[0], sign)"),
     "direct_sign": ("(long double)sign * sinl(ang)", "sinl(ang)"),
     "direct_no_scale": ("      sr /= (long double)n;\n", ""),
+    "sampled_outer_index": ("(unsigned __int128)(a * Sb) * (unsigned __int128)k", "(unsigned __int128)a * (unsigned __int128)k"),
+    "sampled_cross_sign": ("pi += xr * tb[2 * b + 1] + xi * tb[2 * b];", "pi += xr * tb[2 * b + 1] - xi * tb[2 * b];"),
+    "sampled_no_scale": ("out[2 * i] = (double)(sr * sc);", "out[2 * i] = (double)sr;"),
 }
 
 
@@ -53,6 +56,13 @@ def pins_pass(o) -> bool:
         if not close(o.dft_direct(x), brute(x, -1)):
             return False
         if not close(o.dft_direct(x, inverse=True), brute(x, +1) / n):
+            return False
+    for n in (16, 64):
+        x = workloads.normal_batch(n, 1, seed=n + 1)[0]
+        ks = np.arange(n)
+        if not close(o.dft_at(x, ks), brute(x, -1)):
+            return False
+        if not close(o.dft_at(x, ks, inverse=True), brute(x, +1) / n):
             return False
     img = workloads.normal_batch(4 * 8, 1, seed=3).reshape(4, 8)
     if not close(o.fft2(img), np.fft.fft2(img)):
