@@ -194,6 +194,10 @@ def tune_plan(shape, batch, dtype=capi.FFT_C64, reps=10, verbose=False):
     elif info["passes"] == 2:
         lg = int(math.log2(shape[0]))
         splits = [1 << a for a in range(6, 13) if 6 <= lg - a <= 12]
+    elif info["passes"] == 3 and len(shape) == 1:
+        # N1 x N2 x N3: first-pass lengths 2^8..2^12, second-pass 2^5..2^7
+        lg = int(math.log2(shape[0]))
+        splits = [(1 << a, 1 << b) for a in range(8, 13) for b in range(5, 8) if 1 <= lg - a - b <= 14]
     else:
         return "", base[1]
 
@@ -241,6 +245,17 @@ def tune_plan(shape, batch, dtype=capi.FFT_C64, reps=10, verbose=False):
                 descend("", st[1], st[0])
             else:
                 descend("", keys, st)
+    elif isinstance(splits[0], tuple):
+        ranked = []
+        for sp, sp2 in splits:
+            r = run(f"split={sp};split2={sp2}")
+            if r is not None:
+                ranked.append((r[0], sp, sp2))
+        ranked.sort()
+        for _, sp, sp2 in ranked[:2]:
+            n3 = shape[0] // (sp * sp2)
+            descend("", [("a", ROLE_A, sp), ("colt", ROLE_COL_TW, sp2), ("b", ROLE_COL, n3)],
+                    {"split": sp, "split2": sp2})
     else:
         # rank splits by their default variants, then refine the two best
         ranked = []
@@ -326,7 +341,7 @@ def standard_problems():
     from . import workloads
     plans = [([1024], 1, capi.FFT_C64), ([1024], 32768, capi.FFT_C64),
              ([1 << 20], 16, capi.FFT_C64), ([4096, 4096], 1, capi.FFT_C64),
-             ([1 << 16], 64, capi.FFT_C64)]
+             ([1 << 16], 64, capi.FFT_C64), ([1 << 28], 1, capi.FFT_C64)]
     sizes = workloads.uneven_sizes(512, 8, 16, seed=3)
     many = [(list(int(s) for s in sizes), dt) for dt in (capi.FFT_C64, capi.FFT_C16F, capi.FFT_C16BF)]
     return plans, many
