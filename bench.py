@@ -26,6 +26,10 @@ Other modes (used to make the rocprofv3 summaries under profiles/):
                      16 x 2^20 forward and inverse, the 4096^2 image, the
                      512 uneven batch in three storage types, 64 x 2^16
                      forward + adjoint), one JSON line of per-workload rates
+  --mode transfer    host-to-host: the Table 1 sizes (16 .. 65536, one
+                     transform) with the copies included, and a 1 GiB batch
+                     through the chunked pipe (copy in, transform, copy out
+                     overlapped) against the same chunks run one after another
   --mode ablation    the method the paper improves on (Sec. 2.2: one global
                      radix-2 kernel per butterfly level) against the LDS
                      passes, forward 16 x 2^20, one JSON line
@@ -75,7 +79,8 @@ def parse_args(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--mode", choices=["bench", "profile", "ablation", "configs"], default="bench")
+    ap.add_argument("--mode", choices=["bench", "profile", "ablation", "configs", "transfer"],
+                    default="bench")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--summarize-trace", metavar="DIR")
@@ -293,6 +298,77 @@ def configs_report(capi, torch, reps):
     return out
 
 
+def transfer_report(capi, torch, reps):
+    """End-to-end host-to-host timings (pinned host memory)."""
+    import statistics
+    out = {"mode": "transfer", "reps": reps, "table1": [], "pipe": {}}
+    st = torch.cuda.current_stream().cuda_stream
+    for lg in (4, 6, 8, 10, 12, 14, 16):
+        n = 1 << lg
+        h = capi.fft_plan([n], 1, 1, capi.FFT_C64, capi.FFT_FORWARD)
+        xh = torch.randn(n, dtype=torch.complex64).pin_memory()
+        yh = torch.empty_like(xh).pin_memory()
+        xd = torch.empty(n, dtype=torch.complex64, device="cuda")
+        yd = torch.empty_like(xd)
+        e2e, dev_only = [], []
+        for i in range(reps + 5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xd.copy_(xh, non_blocking=True)
+            capi.fft_exec(h, xd.data_ptr(), yd.data_ptr(), st)
+            yh.copy_(yd, non_blocking=True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            capi.fft_exec(h, xd.data_ptr(), yd.data_ptr(), st)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if i >= 5:
+                e2e.append((t1 - t0) * 1e6)
+                dev_only.append((t2 - t1) * 1e6)
+        capi.fft_destroy(h)
+        out["table1"].append({"n": n, "end_to_end_us": round(statistics.median(e2e), 2),
+                              "transform_only_us": round(statistics.median(dev_only), 2)})
+        print(f"[bench] host-to-host N={n}: {statistics.median(e2e):.1f} us", file=sys.stderr, flush=True)
+    # 1 GiB of 2^16-point signals through the pipe, 32 MiB chunks
+    n, batch, chunks = 1 << 16, 64, 32
+    h = capi.fft_plan([n], batch, 1, capi.FFT_C64, capi.FFT_FORWARD)
+    xh = torch.randn(chunks, batch, n, dtype=torch.complex64).pin_memory()
+    yh = torch.empty_like(xh).pin_memory()
+    total_bytes = 2 * xh.numel() * 8
+    res = {}
+    for slots in (1, 3):
+        if slots == 1:
+            # one after another: copy in, transform, copy out per chunk
+            xd = torch.empty(batch, n, dtype=torch.complex64, device="cuda")
+            yd = torch.empty_like(xd)
+            ts = []
+            for r in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for c in range(chunks):
+                    xd.copy_(xh[c], non_blocking=True)
+                    capi.fft_exec(h, xd.data_ptr(), yd.data_ptr(), st)
+                    yh[c].copy_(yd, non_blocking=True)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+        else:
+            p = capi.fft_pipe_create(h, slots)
+            ts = []
+            for r in range(3):
+                t0 = time.perf_counter()
+                capi.fft_pipe_exec(p, xh.data_ptr(), yh.data_ptr(), chunks)
+                capi.fft_pipe_wait(p)
+                ts.append(time.perf_counter() - t0)
+            capi.fft_pipe_destroy(p)
+        t = min(ts)
+        res["serial" if slots == 1 else f"pipe_{slots}_slots"] = {
+            "ms": round(t * 1e3, 3), "host_GBps": round(total_bytes / t / 1e9, 2),
+            "GFLOPs": round(5.0 * n * 16 * batch * chunks / t / 1e9, 1)}
+    capi.fft_destroy(h)
+    out["pipe"] = {"workload": "32 chunks of 64 x 2^16 complex64 (1 GiB in, 1 GiB out), pinned", **res}
+    return out
+
+
 def ablation(capi, torch, lds_plan, sets, nsets, stream, reps):
     """Forward 16 x 2^20 with the LDS passes and with one radix-2 kernel per
     level (log2 N = 20 launches, each moving every point), timed alike."""
@@ -384,6 +460,11 @@ def main(argv=None) -> int:
         del sets
         torch.cuda.empty_cache()
         print(json.dumps(configs_report(capi, torch, args.steps)))
+        return 0
+    if args.mode == "transfer":
+        del sets
+        torch.cuda.empty_cache()
+        print(json.dumps(transfer_report(capi, torch, args.steps)))
         return 0
 
     if args.mode == "profile":

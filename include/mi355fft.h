@@ -276,6 +276,40 @@ int fft_profile_read(fft_plan_t plan, int pass, double *total_ms, int64_t *launc
  */
 int fft_twiddle_host(int64_t count, int64_t R, int64_t M, int64_t mul, float *out);
 
+/*
+ * Host-to-host execution in chunks, with the transfers overlapped.
+ *
+ * The paper times its transforms with the host-to-device and device-to-host
+ * copies included (Sec. 3), finds them dominant for short signals, and names
+ * the transfer as the next thing to improve (Sec. 4).  A pipe runs a plan
+ * over data in host memory: chunk c of `chunks` (each the plan's batch of
+ * transforms, contiguous) is copied in on one stream, transformed on a
+ * second and copied out on a third, so that the copy in of chunk c + 1, the
+ * transform of chunk c and the copy out of chunk c - 1 proceed together.
+ *
+ * fft_pipe_create(plan, slots, &pipe): `slots` >= 2 device staging pairs
+ * (input, output) of one chunk each, three non-blocking streams of default
+ * priority and their events, all owned by the pipe (blocking; allocates).
+ * The plan must outlive the pipe.
+ * fft_pipe_exec(pipe, host_in, host_out, chunks): queues every copy and
+ * transform and returns; host_in / host_out hold chunks * (plan's points)
+ * elements of the plan's type.  Page-locked host memory (hipHostMalloc, or
+ * torch's pin_memory) is needed for the copies to overlap; pageable memory
+ * gives the same results more slowly.  The host buffers must stay valid and
+ * host_in unmodified until fft_pipe_wait returns.  in-place (host_in ==
+ * host_out) is allowed.
+ * fft_pipe_wait(pipe): blocks until the last copy out has finished.
+ * fft_pipe_destroy(pipe): waits, then frees everything the pipe owns; NULL
+ * is a no-op.
+ * Errors: FFT_ERR_INVALID_ARGUMENT (null pointer, slots < 2, chunks < 0),
+ * FFT_ERR_NO_MEMORY, FFT_ERR_HIP.
+ */
+typedef struct fft_pipe_s *fft_pipe_t;
+int fft_pipe_create(fft_plan_t plan, int slots, fft_pipe_t *out);
+int fft_pipe_exec(fft_pipe_t pipe, const void *host_in, void *host_out, int64_t chunks);
+int fft_pipe_wait(fft_pipe_t pipe);
+int fft_pipe_destroy(fft_pipe_t pipe);
+
 #ifdef __cplusplus
 }
 #endif

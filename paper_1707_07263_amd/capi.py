@@ -33,7 +33,8 @@ EXPORTED = (
     "fft_set_workspace", "fft_plan_info", "fft_destroy", "fft_error_string",
     "fft_last_hip_error", "fft_variant_count", "fft_variant_name", "fft_variant_describe",
     "fft_describe", "fft_profile_enable", "fft_profile_collect", "fft_profile_read",
-    "fft_twiddle_host", "fft_describe_many",
+    "fft_twiddle_host", "fft_describe_many", "fft_pipe_create", "fft_pipe_exec", "fft_pipe_wait",
+    "fft_pipe_destroy",
 )
 
 
@@ -93,7 +94,7 @@ def load():
         "fft_plan_many_ex": ([i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, pp],
                              ctypes.c_int),
         "fft_many_watchdog": ([vp, ctypes.c_int], ctypes.c_int),
-        "fft_many_set_wait_limit": ([vp, ctypes.c_int32], ctypes.c_int),
+        "fft_many_set_wait_limit": ([vp, ctypes.c_int64], ctypes.c_int),
         "fft_exec": ([vp, vp, vp, vp], ctypes.c_int),
         "fft_set_scale": ([vp, ctypes.c_double], ctypes.c_int),
         "fft_workspace_size": ([vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -117,6 +118,10 @@ def load():
                               ctypes.c_int),
         "fft_twiddle_host": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                               ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+        "fft_pipe_create": ([vp, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
+        "fft_pipe_exec": ([vp, vp, vp, ctypes.c_int64], ctypes.c_int),
+        "fft_pipe_wait": ([vp], ctypes.c_int),
+        "fft_pipe_destroy": ([vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -216,6 +221,24 @@ def fft_plan_info(plan: int) -> dict:
         "points": info.points, "flops": info.flops, "bytes_min": info.bytes_min,
         "bytes_pass": list(info.bytes_pass)[:info.passes], "gpu_twiddles": info.gpu_twiddles,
     }
+
+
+def fft_pipe_create(plan: int, slots: int = 3) -> int:
+    h = ctypes.c_void_p()
+    _check(load().fft_pipe_create(plan, int(slots), ctypes.byref(h)), "fft_pipe_create")
+    return h.value
+
+
+def fft_pipe_exec(pipe: int, host_in: int, host_out: int, chunks: int) -> None:
+    _check(load().fft_pipe_exec(pipe, host_in, host_out, int(chunks)), "fft_pipe_exec")
+
+
+def fft_pipe_wait(pipe: int) -> None:
+    _check(load().fft_pipe_wait(pipe), "fft_pipe_wait")
+
+
+def fft_pipe_destroy(pipe: int) -> None:
+    _check(load().fft_pipe_destroy(pipe), "fft_pipe_destroy")
 
 
 def fft_destroy(plan: int) -> None:

@@ -1570,3 +1570,122 @@ int fft_twiddle_host(int64_t count, int64_t R, int64_t M, int64_t mul, float* ou
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// host-to-host pipe: copy in, transform and copy out of successive chunks on
+// three streams, ordered per staging slot by events
+// ---------------------------------------------------------------------------
+struct fft_pipe_s {
+  fft_plan_t plan = nullptr;
+  int slots = 0;
+  size_t chunk_bytes = 0;
+  std::vector<void*> d_in, d_out;
+  hipStream_t s_in = nullptr, s_run = nullptr, s_out = nullptr;
+  std::vector<hipEvent_t> ev_in, ev_run, ev_out;
+  int64_t issued = 0;  // chunks queued so far, over every exec of this pipe
+};
+
+namespace {
+
+void pipe_free(fft_pipe_s* q) {
+  if (q->s_out) hipStreamSynchronize(q->s_out);
+  if (q->s_run) hipStreamSynchronize(q->s_run);
+  if (q->s_in) hipStreamSynchronize(q->s_in);
+  for (void* b : q->d_in) if (b) hipFree(b);
+  for (void* b : q->d_out) if (b) hipFree(b);
+  for (auto* v : {&q->ev_in, &q->ev_run, &q->ev_out})
+    for (hipEvent_t e : *v) if (e) hipEventDestroy(e);
+  if (q->s_in) hipStreamDestroy(q->s_in);
+  if (q->s_run) hipStreamDestroy(q->s_run);
+  if (q->s_out) hipStreamDestroy(q->s_out);
+  delete q;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fft_pipe_create(fft_plan_t plan, int slots, fft_pipe_t* out) {
+  if (!out) return FFT_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  if (!plan || slots < 2 || slots > 64) return FFT_ERR_INVALID_ARGUMENT;
+  fft_plan_info_t info;
+  int rc = fft_plan_info(plan, &info);
+  if (rc) return rc;
+  fft_pipe_s* q = new (std::nothrow) fft_pipe_s();
+  if (!q) return FFT_ERR_NO_MEMORY;
+  q->plan = plan;
+  q->slots = slots;
+  q->chunk_bytes = (size_t)info.points * esize(info.dtype);
+  q->d_in.assign(slots, nullptr);
+  q->d_out.assign(slots, nullptr);
+  q->ev_in.assign(slots, nullptr);
+  q->ev_run.assign(slots, nullptr);
+  q->ev_out.assign(slots, nullptr);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < slots && e == hipSuccess; ++i) {
+    e = hipMalloc(&q->d_in[i], std::max<size_t>(q->chunk_bytes, 16));
+    if (e == hipSuccess) e = hipMalloc(&q->d_out[i], std::max<size_t>(q->chunk_bytes, 16));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_in[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_run[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_out[i], hipEventDisableTiming);
+  }
+  // default priority on purpose (no priority streams)
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->s_in, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->s_run, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->s_out, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    pipe_free(q);
+    return e == hipErrorOutOfMemory ? FFT_ERR_NO_MEMORY : hip_fail(e);
+  }
+  *out = q;
+  return FFT_OK;
+}
+
+int fft_pipe_exec(fft_pipe_t q, const void* host_in, void* host_out, int64_t chunks) {
+  if (!q || chunks < 0 || (chunks > 0 && (!host_in || !host_out))) return FFT_ERR_INVALID_ARGUMENT;
+  const char* hi = (const char*)host_in;
+  char* ho = (char*)host_out;
+  for (int64_t c = 0; c < chunks; ++c) {
+    // slots are used round-robin across execs, so that an exec queued before
+    // the previous one finished still waits for the slot it reuses
+    const int64_t g = q->issued++;
+    const int s = (int)(g % q->slots);
+    hipError_t e = hipSuccess;
+    // slot s is free once the copy out of the chunk queued `slots` earlier
+    // has finished (its transform, which read d_in[s], finished before it)
+    if (g >= q->slots) e = hipStreamWaitEvent(q->s_in, q->ev_out[s], 0);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(q->d_in[s], hi + (size_t)c * q->chunk_bytes, q->chunk_bytes,
+                         hipMemcpyHostToDevice, q->s_in);
+    if (e == hipSuccess) e = hipEventRecord(q->ev_in[s], q->s_in);
+    if (e == hipSuccess) e = hipStreamWaitEvent(q->s_run, q->ev_in[s], 0);
+    if (e != hipSuccess) return hip_fail(e);
+    int rc = fft_exec(q->plan, q->d_in[s], q->d_out[s], q->s_run);
+    if (rc) return rc;
+    e = hipEventRecord(q->ev_run[s], q->s_run);
+    if (e == hipSuccess) e = hipStreamWaitEvent(q->s_out, q->ev_run[s], 0);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ho + (size_t)c * q->chunk_bytes, q->d_out[s], q->chunk_bytes,
+                         hipMemcpyDeviceToHost, q->s_out);
+    if (e == hipSuccess) e = hipEventRecord(q->ev_out[s], q->s_out);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return FFT_OK;
+}
+
+int fft_pipe_wait(fft_pipe_t q) {
+  if (!q) return FFT_ERR_INVALID_ARGUMENT;
+  hipError_t e = hipStreamSynchronize(q->s_out);
+  if (e == hipSuccess) e = hipStreamSynchronize(q->s_run);
+  if (e == hipSuccess) e = hipStreamSynchronize(q->s_in);
+  return e == hipSuccess ? FFT_OK : hip_fail(e);
+}
+
+int fft_pipe_destroy(fft_pipe_t q) {
+  if (!q) return FFT_OK;
+  pipe_free(q);
+  return FFT_OK;
+}
+
+}  // extern "C"

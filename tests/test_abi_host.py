@@ -212,3 +212,13 @@ def test_describe_three_pass_1d(lib):
     for bad in ("split2=256", "split=8192;split2=4", "split2=3", "split2=65536"):
         with pytest.raises(capi.FFTError):
             capi.fft_describe([1 << 26], 1, 1, capi.FFT_C64, bad)
+
+
+def test_pipe_argument_errors(lib):
+    import ctypes
+    h = ctypes.c_void_p()
+    assert lib.fft_pipe_create(None, 3, ctypes.byref(h)) == capi.FFT_ERR_INVALID_ARGUMENT
+    assert lib.fft_pipe_create(None, 3, None) == capi.FFT_ERR_INVALID_ARGUMENT
+    assert lib.fft_pipe_exec(None, None, None, 1) == capi.FFT_ERR_INVALID_ARGUMENT
+    assert lib.fft_pipe_wait(None) == capi.FFT_ERR_INVALID_ARGUMENT
+    assert lib.fft_pipe_destroy(None) == capi.FFT_OK
