@@ -400,7 +400,48 @@ def ablation(capi, torch, lds_plan, sets, nsets, stream, reps):
     out["rel_l2_levels_vs_lds"] = (torch.linalg.vector_norm(res["levels"] - res["lds"]) /
                                    torch.linalg.vector_norm(res["lds"])).item()
     capi.fft_destroy(lev)
+    out["matrix_cores"] = mfma_report(capi, torch, reps)
     return out
+
+
+def mfma_report(capi, torch, reps):
+    """256-point transforms: radix-16 stages as matrix-core products against
+    the fastest one-kernel butterfly variant for the same batch, with data
+    from HBM (65536 signals, rotating buffers) and resident in cache (2048
+    signals, one buffer pair)."""
+    names = [capi.fft_variant_name(i) for i in range(capi.fft_variant_count())]
+    butterflies = [n for n in names if n.startswith("r256p") and n.endswith("_c64")]
+    res = {}
+    for batch, label, rotate in ((65536, "hbm", True), (2048, "cache_resident", False)):
+        nb = batch * 256 * 8
+        nsets = max(2, math.ceil(ROT_BYTES / (2 * nb))) if rotate else 1
+        bufs = [(torch.randn(batch * 256, dtype=torch.complex64, device="cuda"),
+                 torch.empty(batch * 256, dtype=torch.complex64, device="cuda")) for _ in range(nsets)]
+        st = torch.cuda.current_stream().cuda_stream
+
+        def timed(sched):
+            h = capi.fft_plan_ex([256], batch, 1, capi.FFT_C64, capi.FFT_FORWARD, sched)
+            for i in range(3):
+                capi.fft_exec(h, bufs[i % nsets][0].data_ptr(), bufs[i % nsets][1].data_ptr(), st)
+            torch.cuda.synchronize()
+            capi.fft_profile_enable(h, reps)
+            for i in range(reps):
+                capi.fft_exec(h, bufs[i % nsets][0].data_ptr(), bufs[i % nsets][1].data_ptr(), st)
+            torch.cuda.synchronize()
+            capi.fft_profile_collect(h)
+            us = 1e3 * capi.fft_profile_read(h, 0)[0] / reps
+            capi.fft_destroy(h)
+            return us
+
+        best = min((timed(f"single={v}"), v) for v in butterflies)
+        mc = timed("method=mfma")
+        res[f"{batch}x256_{label}"] = {
+            "butterflies": {"us": round(best[0], 2), "variant": best[1], "GBps": round(2 * nb / (best[0] * 1e-6) / 1e9, 1),
+                            "of": len(butterflies)},
+            "matrix_cores": {"us": round(mc, 2), "variant": "mfma_dft256", "GBps": round(2 * nb / (mc * 1e-6) / 1e9, 1)},
+            "matrix_cores_over_butterflies_time": round(mc / best[0], 3)}
+        del bufs
+    return res
 
 
 def main(argv=None) -> int:

@@ -23,6 +23,7 @@
 #include "mi355fft.h"
 #include "levels.hpp"
 #include "many.hpp"
+#include "mfma.hpp"
 #include "twiddle.hpp"
 #include "variants.hpp"
 
@@ -122,6 +123,8 @@ struct Schedule {
   bool always_ws = false;
   // one global-memory kernel per radix-2 level instead of LDS passes
   bool levels = false;
+  // 256-point transforms with matrix-core radix-16 stages (experiment)
+  bool mfma = false;
 };
 
 struct Overrides {
@@ -132,6 +135,7 @@ struct Overrides {
   int col3 = -1;  // 2-D columns in two sub-passes: 1 yes, 0 no, -1 automatic
   int64_t split2 = 0;  // three-pass 1-D: second-pass length
   bool levels = false;  // method=levels: the per-level global-memory method
+  bool mfma = false;    // method=mfma: matrix-core radix-16 stages (N = 256)
   std::string a, b, row, col, single, colt;
 };
 
@@ -166,8 +170,9 @@ int parse_schedule(const char* s, Overrides* o) {
       if (val != "0" && val != "1") return FFT_ERR_INVALID_ARGUMENT;
       o->col3 = val == "1";
     } else if (key == "method") {
-      if (val != "lds" && val != "levels") return FFT_ERR_INVALID_ARGUMENT;
+      if (val != "lds" && val != "levels" && val != "mfma") return FFT_ERR_INVALID_ARGUMENT;
       o->levels = val == "levels";
+      o->mfma = val == "mfma";
     } else if (key == "colt") o->colt = val;
     else if (key == "a") o->a = val;
     else if (key == "b") o->b = val;
@@ -369,6 +374,12 @@ int build_schedule_inner(const int64_t* n, int64_t batch, int dims, int dtype, c
       *out = S;
       return FFT_OK;
     }
+    if (ov.mfma) {
+      if (N != 256 || dtype != FFT_C64) return FFT_ERR_INVALID_ARGUMENT;
+      S.mfma = true;
+      *out = S;
+      return FFT_OK;
+    }
     if (l > 2 * kSplitMaxLog2 || ov.split2) {
       int rc = build_three_pass_1d(N, batch, dtype, ov, &S);
       if (rc) return rc;
@@ -443,7 +454,7 @@ int build_schedule_inner(const int64_t* n, int64_t batch, int dims, int dtype, c
     }
   } else {
     const int64_t R = n[0], C = n[1];
-    if (ov.levels) return FFT_ERR_INVALID_ARGUMENT;  // 1-D only
+    if (ov.levels || ov.mfma) return FFT_ERR_INVALID_ARGUMENT;  // 1-D only
     if (!pow2(R) || !pow2(C) || ilog2_64(R) > FFT_MAX_LOG2_2D || ilog2_64(C) > FFT_MAX_LOG2_2D)
       return FFT_ERR_UNSUPPORTED_SIZE;
     if (batch > ((int64_t)1 << 40) / (R * C)) return FFT_ERR_UNSUPPORTED_SIZE;
@@ -506,7 +517,7 @@ int build_schedule_inner(const int64_t* n, int64_t batch, int dims, int dtype, c
 }
 
 int apply_xcd(const std::string& mask, Schedule* S) {
-  if (S->levels) return mask == "0" || mask == "1" ? FFT_OK : FFT_ERR_INVALID_ARGUMENT;
+  if (S->levels || S->mfma) return mask == "0" || mask == "1" ? FFT_OK : FFT_ERR_INVALID_ARGUMENT;
   const size_t n = S->passes.size();
   if (mask.size() != 1 && mask.size() != n) return FFT_ERR_INVALID_ARGUMENT;
   for (size_t i = 0; i < n; ++i)
@@ -535,7 +546,8 @@ int build_schedule(const int64_t* n, int64_t batch, int dims, int dtype, const c
 // plan object
 // ---------------------------------------------------------------------------
 struct fft_plan_s {
-  int kind = 0;  // 0 = strided passes, 1 = batched uneven (many), 2 = per-level method
+  int kind = 0;  // 0 = strided passes, 1 = batched uneven (many), 2 = per-level method,
+                 // 3 = matrix-core 256-point transforms
   void* lv_buf = nullptr;  // kind 2: ping-pong buffer (also listed in aux)
   int cus = 0;
   int64_t n[2] = {1, 1};
@@ -807,7 +819,7 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
   if (rc) return rc;
   fft_plan_s* p = new (std::nothrow) fft_plan_s();
   if (!p) return FFT_ERR_NO_MEMORY;
-  p->kind = S.levels ? 2 : 0;
+  p->kind = S.levels ? 2 : S.mfma ? 3 : 0;
   p->dims = dims;
   p->n[0] = n[0];
   p->n[1] = dims == 2 ? n[1] : 1;
@@ -842,6 +854,7 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
     }
   }
   if (S.levels) tb.add(n[0] / 2, 0, n[0], 1);  // W_N^m, m < N/2
+  if (S.mfma) tb.add(256, 0, 256, 1);          // W_256^m, m < 256
   const bool on_gpu = dims == 1 && ilog2_64(n[0]) >= kGpuTwiddleMinLog2;
   rc = upload_tables(p, tb, on_gpu);
   if (rc) {
@@ -980,6 +993,17 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
   const bool overlap = ib < ob + bytes && ob < ib + bytes;
   const bool same = in == out;
   if (overlap && !same) return FFT_ERR_INPLACE;
+  if (p->kind == 3) {
+    hipEvent_t* slot = prof_slot(p);
+    if (slot) hipEventRecord(slot[0], s);
+    const bool inv = p->direction > 0;
+    const float sc = p->scale_user ? (float)p->scale : (inv ? 1.0f / 256.0f : 1.0f);
+    hipError_t e = launch_dft256_mfma(in, out, p->batch, p->d_tables, sc, inv ? 1 : 0, inv ? 1 : 0, s);
+    if (slot) hipEventRecord(slot[1], s);
+    if (e != hipSuccess) return hip_fail(e);
+    prof_commit(p);
+    return FFT_OK;
+  }
   if (p->kind == 2) {
     LevelsArgs la;
     la.in = in;
@@ -1078,6 +1102,15 @@ int fft_plan_info(fft_plan_t p, fft_plan_info_t* info) {
     return FFT_OK;
   }
   const Schedule& S = p->sched;
+  if (p->kind == 3) {
+    info->passes = 1;
+    snprintf(info->pass_variant[0], 32, "%s", "mfma_dft256");
+    info->points = S.points;
+    info->flops = 5.0 * 256.0 * 8.0 * (double)p->batch;
+    info->bytes_min = 2.0 * es * (double)S.points;
+    info->bytes_pass[0] = 2.0 * es * (double)S.points;
+    return FFT_OK;
+  }
   if (p->kind == 2) {
     // the whole sequence of log2 N level launches is reported as one entry
     const double lg = (double)ilog2_64(p->n[0]);
@@ -1154,11 +1187,12 @@ int fft_describe(const int64_t* n, int64_t batch, int dims, int dtype, const cha
   Schedule S;
   int rc = build_schedule(n, batch, dims, dtype, schedule, &S);
   if (rc) return rc;
-  if (passes) *passes = S.levels ? 1 : (int)S.passes.size();
+  if (passes) *passes = (S.levels || S.mfma) ? 1 : (int)S.passes.size();
   if (names)
     for (size_t i = 0; i < 4; ++i)
       snprintf(names[i], 32, "%s",
                S.levels ? (i == 0 ? "levels_radix2" : "")
+               : S.mfma ? (i == 0 ? "mfma_dft256" : "")
                         : i < S.passes.size() ? (S.passes[i].v ? S.passes[i].v->name : "copy_scale") : "");
   if (split) {
     split[0] = S.split[0];
