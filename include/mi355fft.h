@@ -261,7 +261,8 @@ int fft_describe(const int64_t *n, int64_t batch, int dims, int dtype,
  * the elapsed time of every pending exec's launches to running totals, and
  * fft_profile_read(plan, pass, &ms, &count) returns the total milliseconds
  * and the number of timed launches of pass `pass` (0-based launch index
- * within one exec).
+ * within one exec).  Execs queued on a stream that is being captured into a
+ * graph are not timed (their events could not be read back from replays).
  */
 int fft_profile_enable(fft_plan_t plan, int slots);
 int fft_profile_collect(fft_plan_t plan);

@@ -791,13 +791,20 @@ int tile_lines(int lg, int P, int threads) {
 namespace {
 
 // Event pair array of the next profiling slot, or nullptr when profiling is off.
-hipEvent_t* prof_slot(fft_plan_s* p) {
-  if (!p->prof || p->prof_slots <= 0) return nullptr;
+// Timing events are not recorded into a stream that is being captured into
+// a graph (their elapsed times cannot be read back from graph replays).
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+hipEvent_t* prof_slot(fft_plan_s* p, hipStream_t s) {
+  if (!p->prof || p->prof_slots <= 0 || capturing(s)) return nullptr;
   return p->ev.data() + (size_t)p->prof_next * 2 * p->prof_npass;
 }
 
-void prof_commit(fft_plan_s* p) {
-  if (!p->prof || p->prof_slots <= 0) return;
+void prof_commit(fft_plan_s* p, hipStream_t s) {
+  if (!p->prof || p->prof_slots <= 0 || capturing(s)) return;
   p->prof_next = (p->prof_next + 1) % p->prof_slots;
   p->prof_pending = std::min(p->prof_pending + 1, p->prof_slots);
 }
@@ -978,12 +985,12 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   if (p->kind == 1) {
     if (p->many.has_split && in == out) return FFT_ERR_INPLACE;
-    hipEvent_t* slot = prof_slot(p);
+    hipEvent_t* slot = prof_slot(p, s);
     if (slot) hipEventRecord(slot[0], s);
     hipError_t e = many_launch(p->many, in, out, p->ws, (float)p->scale, p->scale_user, p->direction > 0, s);
     if (slot) hipEventRecord(slot[1], s);
     if (e != hipSuccess) return hip_fail(e);
-    prof_commit(p);
+    prof_commit(p, s);
     return FFT_OK;
   }
   const Schedule& S = p->sched;
@@ -994,14 +1001,14 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
   const bool same = in == out;
   if (overlap && !same) return FFT_ERR_INPLACE;
   if (p->kind == 3) {
-    hipEvent_t* slot = prof_slot(p);
+    hipEvent_t* slot = prof_slot(p, s);
     if (slot) hipEventRecord(slot[0], s);
     const bool inv = p->direction > 0;
     const float sc = p->scale_user ? (float)p->scale : (inv ? 1.0f / 256.0f : 1.0f);
     hipError_t e = launch_dft256_mfma(in, out, p->batch, p->d_tables, sc, inv ? 1 : 0, inv ? 1 : 0, s);
     if (slot) hipEventRecord(slot[1], s);
     if (e != hipSuccess) return hip_fail(e);
-    prof_commit(p);
+    prof_commit(p, s);
     return FFT_OK;
   }
   if (p->kind == 2) {
@@ -1017,12 +1024,12 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
     la.user_scale = p->scale_user;
     la.inverse = p->direction > 0;
     la.cus = p->cus;
-    hipEvent_t* slot = prof_slot(p);
+    hipEvent_t* slot = prof_slot(p, s);
     if (slot) hipEventRecord(slot[0], s);
     hipError_t e = launch_levels(la, s);
     if (slot) hipEventRecord(slot[1], s);
     if (e != hipSuccess) return hip_fail(e);
-    prof_commit(p);
+    prof_commit(p, s);
     return FFT_OK;
   }
   void* ws = nullptr;
@@ -1032,7 +1039,7 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
   }
   if (S.always_ws && !p->ws) return FFT_ERR_INPLACE;
   const bool inv = p->direction > 0;
-  hipEvent_t* slot = prof_slot(p);
+  hipEvent_t* slot = prof_slot(p, s);
   for (size_t i = 0; i < S.passes.size(); ++i) {
     const PassSpec& ps = S.passes[i];
     // out of place: each pass reads `in` (first) or `out` and writes `out`;
@@ -1077,7 +1084,7 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
     if (slot) hipEventRecord(slot[2 * i + 1], s);
     if (e != hipSuccess) return hip_fail(e);
   }
-  prof_commit(p);
+  prof_commit(p, s);
   return FFT_OK;
 }
 

@@ -132,3 +132,32 @@ def test_16bit_4096x4096_image(dev, tname):
                       4096 * 4096)
     print(f"{tname} 4096x4096 image rel-L2 {err.max():.3e}")
     assert err.max() <= TOL16[tname], float(err.max())
+
+
+def test_profiling_skips_graph_capture(dev):
+    # timing events stay out of captured graphs; eager execs are still timed
+    n, b = 1 << 16, 4
+    x = to_gpu_c64(workloads.normal_batch(n, b, seed=5).astype(np.complex64), dev)
+    y = torch.empty_like(x)
+    h = capi.fft_plan([n], b, 1, capi.FFT_C64, capi.FFT_FORWARD)
+    try:
+        capi.fft_profile_enable(h, 8)
+        capi.fft_exec(h, x.data_ptr(), y.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                capi.fft_exec(h, x.data_ptr(), y.data_ptr(), s.cuda_stream)
+        torch.cuda.current_stream().wait_stream(s)
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        capi.fft_profile_collect(h)
+        ms, count = capi.fft_profile_read(h, 0)
+        assert count == 1 and ms > 0
+        ref = oracle.fft(x.cpu().numpy())
+        assert rel_l2_rows(y.cpu().numpy(), ref, n).max() <= tol_fp32(n)
+        del g
+    finally:
+        capi.fft_destroy(h)
