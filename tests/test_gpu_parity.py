@@ -379,23 +379,41 @@ def test_long_column_variants(dev, name):
 
 @pytest.mark.parametrize("name", COL_TWIDDLE)
 def test_column_twiddle_variants(dev, name):
-    # every first column sub-pass variant in a three-pass 2-D plan
+    # every first column sub-pass variant in a three-pass 2-D plan, in its
+    # storage type
     m = re.match(r"t(\d+)p(\d+)w(\d+)", name)
     sq, w = int(m.group(1)), int(m.group(3))
-    dt = {"c64": capi.FFT_C64, "f16": capi.FFT_C16F, "bf16": capi.FFT_C16BF}[name.split("_")[1]]
-    if dt != capi.FFT_C64:
-        pytest.skip("complex64 variant test")
+    dts = name.split("_")[1]
+    dt = {"c64": capi.FFT_C64, "f16": capi.FFT_C16F, "bf16": capi.FFT_C16BF}[dts]
     r, c, sched = sq * sq, max(w, 16), f"col3=1;colt={name}"
     try:
         capi.fft_describe([r, c], 2, 2, dt, sched)
     except capi.FFTError:
         # few rows: long rows, so a row tile of two rows exists
-        c, sched = 4096, sched + ";row=r4096p16w2_c64"
-        capi.fft_describe([r, c], 2, 2, dt, sched)
+        c, sched = 4096, sched + f";row=r4096p16w2_{dts}"
+        try:
+            capi.fft_describe([r, c], 2, 2, dt, sched)
+        except capi.FFTError:
+            pytest.skip("no three-pass plan with this variant")
     x = workloads.normal_batch(r * c, 2, seed=sq + w).reshape(2, r, c)
-    got = run_c64(x, [r, c], schedule=sched, dev=dev)
-    ref = oracle.fft2(x.astype(np.complex64))
-    assert rel_l2_rows(got.reshape(2, -1), ref.reshape(2, -1), r * c).max() <= tol_fp32(r * c)
+    if dt == capi.FFT_C64:
+        got = run_c64(x, [r, c], schedule=sched, dev=dev)
+        ref = oracle.fft2(x.astype(np.complex64))
+        assert rel_l2_rows(got.reshape(2, -1), ref.reshape(2, -1), r * c).max() <= tol_fp32(r * c)
+        return
+    from gpu_helpers import from_gpu_16, quantised, to_gpu_16
+    tdt = torch.float16 if dt == capi.FFT_C16F else torch.bfloat16
+    xt = to_gpu_16(x, dev, tdt)
+    out = torch.empty_like(xt)
+    h = capi.fft_plan_ex([r, c], 2, 2, dt, capi.FFT_FORWARD, sched)
+    try:
+        capi.fft_exec(h, xt.data_ptr(), out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+    finally:
+        capi.fft_destroy(h)
+    ref = oracle.fft2(quantised(x, tdt))
+    err = rel_l2_rows(from_gpu_16(out).reshape(2, -1), ref.reshape(2, -1), r * c)
+    assert err.max() <= (1e-3 if dt == capi.FFT_C16F else 8e-3), float(err.max())
 
 
 THREE_PASS_1D = [(1 << 12, "split=64;split2=16"), (1 << 16, "split=256;split2=8"),
