@@ -518,6 +518,14 @@ __global__ void __launch_bounds__(NT, 1) k_many_pipe(ManyArgs a) {
       tw_base = cmul(pre.hin, pre.lon);
     }
     const bool has_next = nxt < a.n_items;
+    if (has_next && !ready) {
+      // checked two items ahead and not ready then: look again now, so that
+      // its loads can still overlap this item's butterflies
+      lds_barrier();  // every lane has read s_ready
+      if (tid == 0) s_ready = check(nxt);
+      __syncthreads();  // thread 0's acquire precedes every lane's loads
+      ready = s_ready;
+    }
     if (has_next && ready && dn.lg >= 1) many_prefetch<P, NT, TS>(a, dn, xn, pre, tid);
     const int nxt2 = nxt + G;
     ManyItem dn2{};
