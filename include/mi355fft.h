@@ -253,7 +253,9 @@ int fft_describe(const int64_t *n, int64_t batch, int dims, int dtype,
 
 /*
  * Per-launch timing with HIP events recorded on the exec stream around each
- * kernel.  fft_profile_enable(plan, slots) with slots >= 1 creates events for
+ * kernel (timing-only events, recorded without a system-scope fence so that
+ * they do not write back and invalidate caches between passes).
+ * fft_profile_enable(plan, slots) with slots >= 1 creates events for
  * `slots` execs (blocking) and clears the totals; every later fft_exec
  * records its launches into the next slot (a ring: execs beyond `slots`
  * between two collects overwrite the oldest).  slots = 0 turns timing off.
@@ -263,8 +265,13 @@ int fft_describe(const int64_t *n, int64_t batch, int dims, int dtype,
  * and the number of timed launches of pass `pass` (0-based launch index
  * within one exec).  Execs queued on a stream that is being captured into a
  * graph are not timed (their events could not be read back from replays).
+ * fft_profile_sample(plan, every) times only one exec in `every` (the first,
+ * then every `every`-th after it; default 1), so that the events' own cost
+ * is spread thin over a long timed run; FFT_ERR_INVALID_ARGUMENT if
+ * every < 1.  It restarts the count; enabling keeps the setting.
  */
 int fft_profile_enable(fft_plan_t plan, int slots);
+int fft_profile_sample(fft_plan_t plan, int every);
 int fft_profile_collect(fft_plan_t plan);
 int fft_profile_read(fft_plan_t plan, int pass, double *total_ms, int64_t *launches);
 

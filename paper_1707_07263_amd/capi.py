@@ -32,7 +32,7 @@ EXPORTED = (
     "fft_many_set_wait_limit", "fft_exec", "fft_set_scale", "fft_workspace_size",
     "fft_set_workspace", "fft_plan_info", "fft_destroy", "fft_error_string",
     "fft_last_hip_error", "fft_variant_count", "fft_variant_name", "fft_variant_describe",
-    "fft_describe", "fft_profile_enable", "fft_profile_collect", "fft_profile_read",
+    "fft_describe", "fft_profile_enable", "fft_profile_sample", "fft_profile_collect", "fft_profile_read",
     "fft_twiddle_host", "fft_describe_many", "fft_pipe_create", "fft_pipe_exec", "fft_pipe_wait",
     "fft_pipe_destroy",
 )
@@ -110,6 +110,7 @@ def load():
                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER((ctypes.c_char * 32) * 4),
                           i64p], ctypes.c_int),
         "fft_profile_enable": ([vp, ctypes.c_int], ctypes.c_int),
+        "fft_profile_sample": ([vp, ctypes.c_int], ctypes.c_int),
         "fft_profile_collect": ([vp], ctypes.c_int),
         "fft_profile_read": ([vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), i64p], ctypes.c_int),
         "fft_describe_many": ([i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_char_p,
@@ -281,6 +282,11 @@ def fft_describe(n, batch, dims, dtype, schedule=None) -> dict:
 def fft_profile_enable(plan: int, slots: int = 1) -> None:
     """Time the next `slots` execs per launch with HIP events (0: off)."""
     _check(load().fft_profile_enable(plan, int(slots)), "fft_profile_enable")
+
+
+def fft_profile_sample(plan: int, every: int) -> None:
+    """Time one exec in `every` (events recorded on those execs only)."""
+    _check(load().fft_profile_sample(plan, int(every)), "fft_profile_sample")
 
 
 def fft_profile_collect(plan: int) -> None:

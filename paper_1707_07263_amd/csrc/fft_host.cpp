@@ -567,6 +567,9 @@ struct fft_plan_s {
   // profiling: a ring of `prof_slots` exec slots, 2 events per launch each
   bool prof = false;
   int prof_slots = 0, prof_next = 0, prof_pending = 0;
+  int prof_every = 1;    // time one exec in `prof_every`
+  int64_t prof_seq = 0;  // execs seen since timing was enabled
+  bool prof_take = false;
   size_t prof_npass = 0;
   std::vector<hipEvent_t> ev;
   std::vector<double> prof_ms;
@@ -799,12 +802,15 @@ bool capturing(hipStream_t s) {
 }
 
 hipEvent_t* prof_slot(fft_plan_s* p, hipStream_t s) {
+  p->prof_take = false;
   if (!p->prof || p->prof_slots <= 0 || capturing(s)) return nullptr;
-  return p->ev.data() + (size_t)p->prof_next * 2 * p->prof_npass;
+  p->prof_take = p->prof_seq++ % p->prof_every == 0;
+  return p->prof_take ? p->ev.data() + (size_t)p->prof_next * 2 * p->prof_npass : nullptr;
 }
 
-void prof_commit(fft_plan_s* p, hipStream_t s) {
-  if (!p->prof || p->prof_slots <= 0 || capturing(s)) return;
+void prof_commit(fft_plan_s* p, hipStream_t) {
+  if (!p->prof_take) return;
+  p->prof_take = false;
   p->prof_next = (p->prof_next + 1) % p->prof_slots;
   p->prof_pending = std::min(p->prof_pending + 1, p->prof_slots);
 }
@@ -1216,13 +1222,17 @@ int fft_profile_enable(fft_plan_t p, int slots) {
   p->prof_slots = 0;
   p->prof_next = 0;
   p->prof_pending = 0;
+  p->prof_seq = 0;
   p->prof_npass = p->kind != 0 ? 1 : p->sched.passes.size();
   p->prof_ms.assign(p->prof_npass, 0.0);
   p->prof_n.assign(p->prof_npass, 0);
   if (!slots) return FFT_OK;
   p->ev.resize((size_t)slots * 2 * p->prof_npass);
+  // timing-only events: no system-scope fence (cache writeback and
+  // invalidate) when they are recorded, so that timing a pass does not slow
+  // the pass after it
   for (auto& e : p->ev) {
-    hipError_t r = hipEventCreate(&e);
+    hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     if (r != hipSuccess) return hip_fail(r);
   }
   p->prof_slots = slots;
@@ -1246,6 +1256,13 @@ int fft_profile_collect(fft_plan_t p) {
     }
   }
   p->prof_pending = 0;
+  return FFT_OK;
+}
+
+int fft_profile_sample(fft_plan_t p, int every) {
+  if (!p || every < 1) return FFT_ERR_INVALID_ARGUMENT;
+  p->prof_every = every;
+  p->prof_seq = 0;
   return FFT_OK;
 }
 

@@ -161,3 +161,31 @@ def test_profiling_skips_graph_capture(dev):
         del g
     finally:
         capi.fft_destroy(h)
+
+
+def test_profiling_samples_one_exec_in_k(dev):
+    # fft_profile_sample(plan, 3): of 10 execs, the 1st, 4th, 7th and 10th are
+    # timed; every exec still computes the transform
+    n, b = 1 << 12, 8
+    x = to_gpu_c64(workloads.normal_batch(n, b, seed=6).astype(np.complex64), dev)
+    h = capi.fft_plan([n], b, 1, capi.FFT_C64, capi.FFT_FORWARD)
+    try:
+        capi.fft_profile_enable(h, 8)
+        capi.fft_profile_sample(h, 3)
+        outs = []
+        for _ in range(10):
+            y = torch.empty_like(x)
+            capi.fft_exec(h, x.data_ptr(), y.data_ptr(), torch.cuda.current_stream().cuda_stream)
+            outs.append(y)
+        torch.cuda.synchronize()
+        capi.fft_profile_collect(h)
+        ms, count = capi.fft_profile_read(h, 0)
+        assert count == 4 and ms > 0
+        ref = oracle.fft(x.cpu().numpy())
+        for y in outs:
+            assert rel_l2_rows(y.cpu().numpy(), ref, n).max() <= tol_fp32(n)
+        with pytest.raises(capi.FFTError) as ei:
+            capi.fft_profile_sample(h, 0)
+        assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT
+    finally:
+        capi.fft_destroy(h)
