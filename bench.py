@@ -65,12 +65,19 @@ PROFILE_EVERY = 5
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_fft_n2p20_b16.txt")
 
 
+# sources of other kernel families, which the benchmarked step never runs
+NOT_IN_STEP = ("many.", "levels.", "mfma.", "variants_c16.")
+
+
 def kernel_source_hash() -> str:
-    """Hash of the device sources; a traffic figure is only valid for the
-    kernels it was measured on."""
+    """Hash of the sources the benchmarked step's kernels and launches are
+    built from; a traffic figure is only valid for the kernels it was
+    measured on."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1707_07263_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
+        if f.startswith(NOT_IN_STEP):
+            continue
         if f.endswith((".hpp", ".hip", ".cpp", ".py")):
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(f.encode())

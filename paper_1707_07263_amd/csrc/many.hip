@@ -649,8 +649,8 @@ int blocks_many() {
 
 #define MANY_VARIANT(TS, DT, P, NT) \
   {DT, P, NT, 0, kManyMaxLg, &launch_many<TS, P, NT>, &blocks_many<TS, P, NT>}
-// pipelined: 512 lanes (one workgroup per CU, tiles up to 2^12) or 256
-// lanes (two per CU, tiles up to 2^11 so that each fits half the LDS)
+// pipelined: 512 lanes (tiles up to 2^12) or 256 lanes (tiles up to 2^11,
+// half the LDS; its registers still keep it to one workgroup per CU)
 #define MANY_PIPE(TS, DT, P, NT, MAXLG) \
   {DT, P, NT, 1, MAXLG, &launch_many_pipe<TS, P, NT, MAXLG>, &blocks_many_pipe<TS, P, NT, MAXLG>}
 
