@@ -226,10 +226,18 @@ def cpu_baseline(x_np, seconds: float):
             "sample": f"{reps} x (forward + inverse of 16 x 2^20 complex, FP64 radix-2) in {el:.1f} s"}
 
 
+def _stats(v):
+    """min, median and 90th percentile of per-repetition times."""
+    v = sorted(v)
+    q = lambda f: v[min(len(v) - 1, int(math.ceil(f * len(v))) - 1)]
+    return {"min": round(v[0], 2), "median": round(q(0.5), 2), "p90": round(q(0.9), 2)}
+
+
 def _time_plans(capi, torch, plans, nbytes_io, reps):
-    """Average device time of running `plans` (each (handle, in/out element
-    count)) back to back, over rotating buffers of >= 1 GiB; per-launch HIP
-    events recorded by the library on the exec stream."""
+    """Device time of running `plans` (each (handle, in/out byte count)) back
+    to back, over rotating buffers of >= 1 GiB; per-launch HIP events
+    recorded by the library on the exec stream.  Returns the mean and the
+    per-repetition times (each repetition synchronised and read on its own)."""
     stream = torch.cuda.current_stream().cuda_stream
     # >= 1 GiB of rotating buffers (at most 64 sets: the latency-bound case
     # is tiny and its working set stays cache-resident regardless)
@@ -243,20 +251,51 @@ def _time_plans(capi, torch, plans, nbytes_io, reps):
             capi.fft_exec(h, x.data_ptr(), y.data_ptr(), stream)
     torch.cuda.synchronize()
     for h, _ in plans:
-        capi.fft_profile_enable(h, reps)
+        capi.fft_profile_enable(h, 1)
+    passes = [capi.fft_plan_info(h)["passes"] for h, _ in plans]
+    per_rep, total = [], 0.0
     for i in range(reps):
         for (h, _), (x, y) in zip(plans, bufs[i % nsets]):
             capi.fft_exec(h, x.data_ptr(), y.data_ptr(), stream)
-    torch.cuda.synchronize()
-    us = 0.0
+        torch.cuda.synchronize()
+        cum = 0.0
+        for (h, _), np_ in zip(plans, passes):
+            capi.fft_profile_collect(h)
+            cum += sum(1e3 * capi.fft_profile_read(h, p)[0] for p in range(np_))
+        per_rep.append(cum - total)
+        total = cum
     for h, _ in plans:
-        capi.fft_profile_collect(h)
-        info = capi.fft_plan_info(h)
-        us += sum(1e3 * capi.fft_profile_read(h, p)[0] / reps for p in range(info["passes"]))
         capi.fft_profile_enable(h, 0)
     del bufs
     torch.cuda.empty_cache()
-    return us
+    return total / reps, per_rep
+
+
+def _time_torch_fft(torch, fn, shapes, reps):
+    """Context only: the vendor FFT that torch calls on this GPU (hipFFT /
+    rocFFT), timed with torch's events on the same shapes over rotating
+    inputs of >= 1 GiB.  Returns per-repetition microseconds, or an error."""
+    try:
+        nbytes = sum(8 * math.prod(sh) for sh in shapes)
+        nsets = min(16, max(2, math.ceil(ROT_BYTES / max(2 * nbytes, 1))))
+        sets = [[torch.randn(*sh, dtype=torch.complex64, device="cuda") for sh in shapes] for _ in range(nsets)]
+        for i in range(3):
+            fn(*sets[i % nsets])
+        torch.cuda.synchronize()
+        out = []
+        for i in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn(*sets[i % nsets])
+            e1.record()
+            torch.cuda.synchronize()
+            out.append(1e3 * e0.elapsed_time(e1))
+        del sets
+        torch.cuda.empty_cache()
+        return out
+    except Exception as ex:  # context only: a vendor failure is reported, not raised
+        torch.cuda.empty_cache()
+        return str(ex)[:200]
 
 
 def configs_report(capi, torch, reps):
@@ -265,9 +304,9 @@ def configs_report(capi, torch, reps):
     from paper_1707_07263_amd import autotune, workloads
     out = {"mode": "configs", "reps": reps, "peak_GBps": PEAK_HBM_GBS, "configs": []}
 
-    def add(name, plans, dtype_bytes, note=""):
+    def add(name, plans, dtype_bytes, note="", vendor=None):
         nbytes = sum(n for _, n in plans)
-        us = _time_plans(capi, torch, plans, 2 * nbytes, reps)
+        us, per_rep = _time_plans(capi, torch, plans, 2 * nbytes, reps)
         flops = sum(capi.fft_plan_info(h)["flops"] for h, _ in plans)
         moved = sum(sum(capi.fft_plan_info(h)["bytes_pass"]) for h, _ in plans)
         minimum = sum(capi.fft_plan_info(h)["bytes_min"] for h, _ in plans)
@@ -276,10 +315,17 @@ def configs_report(capi, torch, reps):
             "method_GBps": round(moved / (us * 1e-6) / 1e9, 1),
             "method_frac": round(moved / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
             "min_GBps": round(minimum / (us * 1e-6) / 1e9, 1),
+            "us_reps": _stats(per_rep),
             "schedules": [capi.fft_plan_info(h)["pass_variant"] for h, _ in plans], "note": note})
         for h, _ in plans:
             capi.fft_destroy(h)
         print(f"[bench] {name}: {us:.2f} us", file=sys.stderr, flush=True)
+        if vendor is not None:
+            fn, shapes, what = vendor
+            t = _time_torch_fft(torch, fn, shapes, reps)
+            out["configs"][-1]["torch_fft"] = ({"what": what, "us": _stats(t)} if isinstance(t, list)
+                                               else {"what": what, "error": t})
+            print(f"[bench]   torch.fft context: {out['configs'][-1]['torch_fft']}", file=sys.stderr, flush=True)
 
     def plan(shape, batch, dtype, direction, scale=None):
         h = capi.fft_plan_ex(list(shape), batch, len(shape), dtype, direction,
@@ -292,20 +338,33 @@ def configs_report(capi, torch, reps):
         return h, n * (8 if dtype == capi.FFT_C64 else 4)
 
     C64 = capi.FFT_C64
-    add("1-D N=1024 batch 1, forward (latency-bound)", [plan([1024], 1, C64, capi.FFT_FORWARD)], 8)
-    add("1-D N=1024 batch 32768, forward", [plan([1024], 32768, C64, capi.FFT_FORWARD)], 8)
+    tf = torch.fft
+    add("1-D N=1024 batch 1, forward (latency-bound)", [plan([1024], 1, C64, capi.FFT_FORWARD)], 8,
+        vendor=(lambda x: tf.fft(x), [(1024,)], "fft"))
+    add("1-D N=1024 batch 32768, forward", [plan([1024], 32768, C64, capi.FFT_FORWARD)], 8,
+        vendor=(lambda x: tf.fft(x), [(32768, 1024)], "fft"))
     add("1-D N=2^20 batch 16, forward then inverse",
-        [plan([N], BATCH, C64, capi.FFT_FORWARD), plan([N], BATCH, C64, capi.FFT_INVERSE)], 8)
-    add("2-D 4096x4096 image, forward", [plan([4096, 4096], 1, C64, capi.FFT_FORWARD)], 8)
+        [plan([N], BATCH, C64, capi.FFT_FORWARD), plan([N], BATCH, C64, capi.FFT_INVERSE)], 8,
+        vendor=(lambda x: tf.ifft(tf.fft(x)), [(BATCH, N)], "ifft(fft(x))"))
+    add("2-D 4096x4096 image, forward", [plan([4096, 4096], 1, C64, capi.FFT_FORWARD)], 8,
+        vendor=(lambda x: tf.fft2(x), [(4096, 4096)], "fft2"))
     add("1-D N=2^28 batch 1, forward (three passes, GPU FP64 twiddles)",
-        [plan([1 << 28], 1, C64, capi.FFT_FORWARD)], 8)
+        [plan([1 << 28], 1, C64, capi.FFT_FORWARD)], 8,
+        vendor=(lambda x: tf.fft(x), [(1 << 28,)], "fft"))
     sizes = [int(v) for v in workloads.uneven_sizes(512, 8, 16, seed=3)]
+    counts = {}
+    for v in sizes:
+        counts[v] = counts.get(v, 0) + 1
+    grouped = [(c, n) for n, c in sorted(counts.items())]
     for dt, name in ((C64, "complex64"), (capi.FFT_C16F, "fp16 pairs"), (capi.FFT_C16BF, "bf16 pairs")):
         h = capi.fft_plan_many_ex(sizes, dt, capi.FFT_FORWARD, autotune.many_schedule_for(sizes, dt))
         add(f"512 uneven 2^8..2^16 in one persistent launch, {name}", [(h, sum(sizes) * (8 if dt == C64 else 4))],
-            8 if dt == C64 else 4)
+            8 if dt == C64 else 4,
+            vendor=((lambda *xs: [tf.fft(x) for x in xs]), grouped, "fft per length (9 batched calls)")
+            if dt == C64 else None)
     add("64 x 2^16 forward + adjoint backward (autograd pair)",
-        [plan([1 << 16], 64, C64, capi.FFT_FORWARD), plan([1 << 16], 64, C64, capi.FFT_INVERSE, 1.0)], 8)
+        [plan([1 << 16], 64, C64, capi.FFT_FORWARD), plan([1 << 16], 64, C64, capi.FFT_INVERSE, 1.0)], 8,
+        vendor=(lambda x: tf.ifft(tf.fft(x), norm="forward"), [(64, 1 << 16)], "ifft(fft(x), norm=forward)"))
     return out
 
 
