@@ -523,7 +523,7 @@ def main(argv=None) -> int:
         print(summarize_pmc(*args.summarize_pmc))
         return 0
     if args.gpus != 1:
-        print("bench.py: this build targets one GPU; --gpus N > 1 is not supported. The batch of "
+        print("bench.py: the library runs on one GPU; --gpus N > 1 is not supported. The batch of "
               "independent transforms would shard by rows with no communication.", file=sys.stderr)
         return 2
 
