@@ -225,8 +225,23 @@ def cpu_baseline(x_np, seconds: float):
         if el >= seconds or reps >= 100:
             break
     flops = reps * 2 * BATCH * 5.0 * N * math.log2(N)
-    return {"value": round(flops / el / 1e9, 3), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": f"{reps} x (forward + inverse of 16 x 2^20 complex, FP64 radix-2) in {el:.1f} s"}
+    out = {"value": round(flops / el / 1e9, 3), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+           "sample": f"{reps} x (forward + inverse of 16 x 2^20 complex, FP64 radix-2) in {el:.1f} s"}
+    # the same oracle on one thread, over single transforms of the batch (a
+    # bounded sample of about a quarter of the time above)
+    oracle.set_threads(1)
+    reps1, t0 = 0, time.perf_counter()
+    while True:
+        row = x_np[reps1 % BATCH:reps1 % BATCH + 1]
+        oracle.fft(oracle.fft(row), inverse=True)
+        reps1 += 1
+        el1 = time.perf_counter() - t0
+        if el1 >= seconds / 4 or reps1 >= 400:
+            break
+    oracle.set_threads(cores)
+    out["single_thread"] = {"value": round(reps1 * 2 * 5.0 * N * math.log2(N) / el1 / 1e9, 3),
+                            "sample": f"{reps1} x (forward + inverse of one 2^20 transform) in {el1:.1f} s"}
+    return out
 
 
 def _stats(v):
