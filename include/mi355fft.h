@@ -183,7 +183,11 @@ int fft_many_set_wait_limit(fft_plan_t plan, int64_t microseconds);
  * hipGraph.  `in` and `out` must not partially overlap; in == out is allowed
  * for one-pass plans, for three-pass plans, and for two-pass plans once a
  * workspace of fft_workspace_size() bytes is set (else FFT_ERR_INPLACE).  Input data are
- * not modified unless in == out.
+ * not modified unless in == out.  A plan may be executed on several streams;
+ * execs that share a workspace (in-place two-pass, three-pass and batched
+ * plans) must not overlap in time, and calls on one plan from several host
+ * threads must be serialised by the caller (the plan's timing state is not
+ * locked).
  */
 int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
 
