@@ -538,6 +538,9 @@ __global__ void __launch_bounds__(NT, 1) k_many_pipe(ManyArgs a) {
     // after the butterflies: every wave's older stores and this prefetch
     // have landed; release the previous A tile, look at the item after next
     auto between = [&]() {
+      // nothing to release and nothing to wait for two items ahead: no
+      // barrier needed (the condition is the same for every lane)
+      if (pending < 0 && (!has_next || nxt2 >= a.n_items || dn2.kind != MANY_B)) return;
       __syncthreads();
       if (tid == 0) {
         if (pending >= 0)
