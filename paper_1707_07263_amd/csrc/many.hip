@@ -538,18 +538,24 @@ __global__ void __launch_bounds__(NT, 1) k_many_pipe(ManyArgs a) {
     // after the butterflies: every wave's older stores and this prefetch
     // have landed; release the previous A tile, look at the item after next
     auto between = [&]() {
-      // nothing to release and nothing to wait for two items ahead: no
-      // barrier needed (the condition is the same for every lane)
-      if (pending < 0 && (!has_next || nxt2 >= a.n_items || dn2.kind != MANY_B)) return;
+      // the release needs every wave's stores of the previous tile ordered
+      // before it (one barrier); the answer of a readiness check needs a
+      // second one.  An item two ahead that is not a second-pass item is
+      // ready: then no answer is broadcast (the condition is the same for
+      // every lane)
+      const bool look = has_next && nxt2 < a.n_items && dn2.kind == MANY_B;
+      if (pending < 0 && !look) return;
       __syncthreads();
       if (tid == 0) {
         if (pending >= 0)
           __hip_atomic_fetch_add(&done[pending], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        s_ready = has_next ? check(nxt2) : 1;
+        if (look) s_ready = check(nxt2);
       }
       pending = -1;
-      __syncthreads();  // thread 0's acquire precedes every lane's later loads
-      ready2 = s_ready;
+      if (look) {
+        __syncthreads();  // thread 0's acquire precedes every lane's later loads
+        ready2 = s_ready;
+      }
     };
 
     switch (d.lg) {
