@@ -364,6 +364,9 @@ def configs_report(capi, torch, reps):
     add("1-D N=2^20 batch 16, forward then inverse",
         [plan([N], BATCH, C64, capi.FFT_FORWARD), plan([N], BATCH, C64, capi.FFT_INVERSE)], 8,
         vendor=(lambda x: tf.ifft(tf.fft(x)), [(BATCH, N)], "ifft(fft(x))"))
+    for dt, name in ((capi.FFT_C16F, "fp16 pairs"), (capi.FFT_C16BF, "bf16 pairs")):
+        add(f"1-D N=2^20 batch 16, forward then inverse, {name}",
+            [plan([N], BATCH, dt, capi.FFT_FORWARD), plan([N], BATCH, dt, capi.FFT_INVERSE)], 4)
     add("2-D 4096x4096 image, forward", [plan([4096, 4096], 1, C64, capi.FFT_FORWARD)], 8,
         vendor=(lambda x: tf.fft2(x), [(4096, 4096)], "fft2"))
     add("1-D N=2^28 batch 1, forward (three passes, GPU FP64 twiddles)",

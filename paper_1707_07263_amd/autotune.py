@@ -336,12 +336,14 @@ def tune_and_store(problems, many=(), reps=10, path=None, verbose=True):
 
 
 def standard_problems():
-    """The workloads this package is benchmarked on (1-D 2^10 and 2^20, 2-D
-    4096^2, batched 2^16, batched uneven sizes in three storage types)."""
+    """The workloads this package is benchmarked on (1-D 2^10 and 2^20, the
+    latter also in 16-bit storage, 2-D 4096^2, batched 2^16, 1-D 2^28,
+    batched uneven sizes in three storage types)."""
     from . import workloads
     plans = [([1024], 1, capi.FFT_C64), ([1024], 32768, capi.FFT_C64),
              ([1 << 20], 16, capi.FFT_C64), ([4096, 4096], 1, capi.FFT_C64),
-             ([1 << 16], 64, capi.FFT_C64), ([1 << 28], 1, capi.FFT_C64)]
+             ([1 << 16], 64, capi.FFT_C64), ([1 << 28], 1, capi.FFT_C64),
+             ([1 << 20], 16, capi.FFT_C16F), ([1 << 20], 16, capi.FFT_C16BF)]
     sizes = workloads.uneven_sizes(512, 8, 16, seed=3)
     many = [(list(int(s) for s in sizes), dt) for dt in (capi.FFT_C64, capi.FFT_C16F, capi.FFT_C16BF)]
     return plans, many

@@ -12,6 +12,7 @@
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
+#include <type_traits>
 #include <stdint.h>
 
 namespace mfft {
@@ -505,8 +506,10 @@ k_pipe(PassArgs a) {
 
   TwLds<L, P>::copy(twl, a.tw, tid, NT);
 
-  // registers of the prefetched tile
-  float2 vn[PP];
+  // registers of the prefetched tile; 16-bit pairs stay in their storage
+  // type (one register each) until they are converted at the top of the loop
+  using PreT = typename std::conditional<sizeof(TS) == 8, float2, TS>::type;
+  PreT vn[PP];
   float2 rown = make_float2(1.f, 0.f), lon = make_float2(1.f, 0.f), hin = make_float2(1.f, 0.f);
   auto prefetch = [&](int64_t tl) {
     const int64_t bat = tl / a.tiles_per_batch;
@@ -517,7 +520,12 @@ k_pipe(PassArgs a) {
                     (int64_t)ln * a.in_line + (int64_t)t_ld * a.in_elem;
     const int64_t step = (int64_t)T * a.in_elem;
 #pragma unroll
-    for (int q = 0; q < PP; ++q) vn[q] = load_c(src + q * step);
+    for (int q = 0; q < PP; ++q) {
+      if constexpr (sizeof(TS) == 8)
+        vn[q] = load_c(src + q * step);
+      else
+        vn[q] = src[q * step];
+    }
     if (TWID) {
       // this tile's step rows W_N^{row*q*T} (one entry per lane) and the
       // lane's base W_N^{row*t}, row = line >> tw_line_shift
@@ -538,7 +546,10 @@ k_pipe(PassArgs a) {
     float2 v[PP];
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
-      v[q] = vn[q];
+      if constexpr (sizeof(TS) == 8)
+        v[q] = vn[q];
+      else
+        v[q] = load_c(&vn[q]);
       v[q].y = __uint_as_float(__float_as_uint(v[q].y) ^ sgn_in);
     }
     float2 tw_base = make_float2(1.f, 0.f);

@@ -132,6 +132,11 @@ def c16_set():
     for lg in range(11, 13):
         if ok(1 << lg, 16, 2):
             out.append(("r", 1 << lg, 16, 2, 0))
+    # the split passes of 2^16 and 2^20 with the next tile prefetched (a
+    # sixth entry 1: persistent; the prefetch holds 16-bit pairs, one register
+    # each) or 128 B row segments (32 pairs per row)
+    out += [("a", 1024, 32, 16, 0, 1), ("c", 1024, 32, 16, 1, 1),
+            ("a", 256, 16, 32, 0, 1), ("c", 256, 16, 32, 0, 1), ("c", 256, 16, 32, 0)]
     return list(dict.fromkeys(out))
 
 
@@ -204,7 +209,7 @@ def main():
     emit("variants_c64_col2.hip", "add_variants_c64_col2", cols[half:])
     items = []
     for dt in ("f16", "bf16"):
-        items += [v + (dt,) for v in c16_set()]
+        items += [v[:5] + (dt,) + v[5:] for v in c16_set()]
     emit("variants_c16.hip", "add_variants_c16", items)
     emit("variants_c64_pipe.hip", "add_variants_c64_pipe",
          [v + ("c64", 1) for v in pipe_set()] + [("t",) + v + ("c64",) for v in coltw_set()])

@@ -303,7 +303,7 @@ def _variant_names(prefix_filter):
             if prefix_filter(c.fft_variant_name(i))]
 
 
-PERSISTENT = sorted(n for n in _variant_names(lambda s: "q" in s.split("_")[0]))
+PERSISTENT = sorted(n for n in _variant_names(lambda s: "q" in s.split("_")[0] and s.endswith("_c64")))
 
 
 @pytest.mark.parametrize("name", PERSISTENT)

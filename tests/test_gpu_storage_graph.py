@@ -189,3 +189,42 @@ def test_profiling_samples_one_exec_in_k(dev):
         assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT
     finally:
         capi.fft_destroy(h)
+
+
+def _variants_16(kind):
+    return sorted(capi.fft_variant_name(i) for i in range(capi.fft_variant_count())
+                  if capi.fft_variant_name(i).endswith("_" + kind) and "q" in capi.fft_variant_name(i).split("_")[0])
+
+
+@pytest.mark.parametrize("name", _variants_16("f16") + _variants_16("bf16"))
+def test_16bit_persistent_variants(dev, name):
+    # every persistent 16-bit variant through a plan that uses it (more tiles
+    # than resident workgroups), forward and inverse, against the oracle on
+    # the quantised input
+    tname = "float16" if name.endswith("_f16") else "bfloat16"
+    code = capi.FFT_C16F if tname == "float16" else capi.FFT_C16BF
+    tdt = getattr(torch, tname)
+    i = [capi.fft_variant_name(k) for k in range(capi.fft_variant_count())].index(name)
+    d = capi.fft_variant_describe(i)
+    L = d["L"]
+    if d["role"] == 1:
+        n, sched = L * 512, f"split={L};a={name}"
+    else:
+        n, sched = 512 * L, f"split=512;b={name}"
+    b = 3
+    x = workloads.normal_batch(n, b, seed=L + 7)
+    xq = quantised(x, tdt)
+    xt = to_gpu_16(x, dev, tdt)
+    st = torch.cuda.current_stream().cuda_stream
+    for direction in (capi.FFT_FORWARD, capi.FFT_INVERSE):
+        h = capi.fft_plan_ex([n], b, 1, code, direction, sched)
+        try:
+            y = torch.empty_like(xt)
+            capi.fft_exec(h, xt.data_ptr(), y.data_ptr(), st)
+            torch.cuda.synchronize()
+        finally:
+            capi.fft_destroy(h)
+        got = from_gpu_16(y).reshape(b, -1)
+        ref = oracle.fft(xq, inverse=direction == capi.FFT_INVERSE).reshape(b, -1)
+        err = rel_l2_rows(got, ref, n)
+        assert err.max() <= TOL16[tname], (name, direction, float(err.max()))
