@@ -535,8 +535,9 @@ __global__ void __launch_bounds__(NT, 1) k_many_pipe(ManyArgs a) {
       if (dn2.kind != MANY_SINGLE) xn2 = a.xf[dn2.a];
     }
     int ready2 = 1;
-    // after the butterflies: every wave's older stores and this prefetch
-    // have landed; release the previous A tile, look at the item after next
+    // after the butterflies: release the previous A tile, look at the item
+    // after next (thread 0 waits for its wave's memory operations first, this
+    // prefetch included, which is the time the butterflies hide)
     auto between = [&]() {
       // the release needs every wave's stores of the previous tile ordered
       // before it (one barrier); the answer of a readiness check needs a
