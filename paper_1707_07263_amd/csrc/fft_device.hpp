@@ -385,6 +385,15 @@ __device__ __forceinline__ void run_stages(float2* v, void* lds, int& m, int& t,
 // footprint lets onto a CU can be resident (4 SIMDs per CU, at most 8 waves
 // per SIMD, 160 KB of LDS per CU); passed to the register allocator, capped
 // at 4 waves (128 VGPRs) so that no variant is squeezed into spilling.
+// Only row passes (contiguous lines in and out) take a line map; for the
+// other lane mappings the persistent pass knows it is absent at compile
+// time, so its loop carries no load whose result the next tile's addresses
+// would wait for.
+template <int LOADM, int STOREM>
+__host__ __device__ constexpr bool kLineMap() {
+  return LOADM == 0 && STOREM == 0;
+}
+
 template <int L, int P, int W, int EX>
 __host__ __device__ constexpr int strip_min_waves() {
   constexpr int nt = W * Sched<L, P>::T;
@@ -496,11 +505,19 @@ k_pipe(PassArgs a) {
   float2* twl = lds + XN;
   float2* rowl = lds + XN + TwLds<L, P>::SIZE;
 
-  const int tid = threadIdx.x;
-  const int m_ld = LOADM ? tid % W : tid / T;
-  const int t_ld = LOADM ? tid / W : tid % T;
-  const int m_st = STOREM ? tid % W : tid / T;
-  const int t_st = STOREM ? tid / W : tid % T;
+  int tid = threadIdx.x;
+  int m_ld, t_ld, m_st, t_st;
+  // lane indices, recomputed from an opaque copy of the lane id once per
+  // tile: values derived from them are then cheap to rebuild in the loop
+  // and are not held in registers across it
+  auto lanes = [&]() {
+    asm volatile("" : "+v"(tid));
+    m_ld = LOADM ? tid % W : tid / T;
+    t_ld = LOADM ? tid / W : tid % T;
+    m_st = STOREM ? tid % W : tid / T;
+    t_st = STOREM ? tid / W : tid % T;
+  };
+  lanes();
   const uint32_t sgn_in = a.conj_in ? 0x80000000u : 0u;
   const uint32_t sgn_out = a.conj_out ? 0x80000000u : 0u;
 
@@ -515,7 +532,8 @@ k_pipe(PassArgs a) {
     const int64_t bat = tl / a.tiles_per_batch;
     const int line0 = (int)(tl - bat * a.tiles_per_batch) * W;
     const int tib = (int)(tl - bat * a.tiles_per_batch);
-    const int ln = a.line_map ? a.line_map[tib * W + m_ld] : min(line0 + m_ld, a.lines - 1);
+    const int ln = (kLineMap<LOADM, STOREM>() && a.line_map) ? a.line_map[tib * W + m_ld]
+                                                              : min(line0 + m_ld, a.lines - 1);
     const TS* src = reinterpret_cast<const TS*>(a.in) + bat * a.in_batch +
                     (int64_t)ln * a.in_line + (int64_t)t_ld * a.in_elem;
     const int64_t step = (int64_t)T * a.in_elem;
@@ -529,7 +547,7 @@ k_pipe(PassArgs a) {
     if (TWID) {
       // this tile's step rows W_N^{row*q*T} (one entry per lane) and the
       // lane's base W_N^{row*t}, row = line >> tw_line_shift
-      if (tid < W * PP)
+      if (W * PP == NT || tid < W * PP)
         rown = a.tw_step[(int64_t)((uint32_t)min(line0 + tid / PP, a.lines - 1) >> a.tw_line_shift) * PP +
                          (tid % PP)];
       const uint32_t jb = ((uint32_t)min(line0 + m_st, a.lines - 1) >> a.tw_line_shift) * (uint32_t)t_st;
@@ -543,6 +561,7 @@ k_pipe(PassArgs a) {
   if (tile < a.total_tiles) prefetch(tile);
   lds_barrier();  // stage twiddles visible
   for (; tile < a.total_tiles; tile += gridDim.x) {
+    lanes();
     float2 v[PP];
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
@@ -554,7 +573,7 @@ k_pipe(PassArgs a) {
     }
     float2 tw_base = make_float2(1.f, 0.f);
     if (TWID) {
-      if (tid < W * PP) rowl[tid] = rown;
+      if (W * PP == NT || tid < W * PP) rowl[tid] = rown;
       tw_base = cmul(hin, lon);
     }
     const int64_t bat = tile / a.tiles_per_batch;
@@ -567,20 +586,25 @@ k_pipe(PassArgs a) {
     if (TWID) lds_barrier();  // step rows visible (also when no exchange ran)
 
     const int tib = (int)(tile - bat * a.tiles_per_batch);
-    const int line = a.line_map ? row_transpose(a.line_map[tib * W + m], a.tr_shift) : line0 + m;
-    const bool ok = a.line_map ? true : line < a.lines;
-    TS* dst = reinterpret_cast<TS*>(a.out) + bat * a.out_batch + (int64_t)line * a.out_line +
+    const bool lmap = kLineMap<LOADM, STOREM>() && a.line_map;
+    const int line = lmap ? row_transpose(a.line_map[tib * W + m], a.tr_shift) : line0 + m;
+    // rows past the end of a partial strip loaded a copy of the last line and
+    // computed exactly its result (same data, same twiddles, same order of
+    // operations): they store it over the last line, the same bits.  Every
+    // lane stores, so the number of memory operations after the prefetch is
+    // the same on every path and the top of the loop waits for the prefetch
+    // only, not for these stores.
+    const int line_st = lmap ? line : min(line, a.lines - 1);
+    TS* dst = reinterpret_cast<TS*>(a.out) + bat * a.out_batch + (int64_t)line_st * a.out_line +
               (int64_t)t * a.out_elem;
     const int64_t step = (int64_t)T * a.out_elem;
-    if (ok) {
 #pragma unroll
-      for (int q = 0; q < PP; ++q) {
-        float2 y = v[q];
-        if (TWID) y = cmul(y, cmul(tw_base, rowl[m * PP + q]));
-        y = cscale(y, a.scale);
-        y.y = __uint_as_float(__float_as_uint(y.y) ^ sgn_out);
-        store_c(dst + q * step, y);
-      }
+    for (int q = 0; q < PP; ++q) {
+      float2 y = v[q];
+      if (TWID) y = cmul(y, cmul(tw_base, rowl[m * PP + q]));
+      y = cscale(y, a.scale);
+      y.y = __uint_as_float(__float_as_uint(y.y) ^ sgn_out);
+      store_c(dst + q * step, y);
     }
     lds_barrier();  // LDS reads of this tile done before the next one overwrites
   }
