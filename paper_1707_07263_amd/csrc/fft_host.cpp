@@ -990,6 +990,10 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
   if (check_ptr(in, p->dtype) || check_ptr(out, p->dtype)) return FFT_ERR_ALIGNMENT;
   hipStream_t s = (hipStream_t)stream;
   if (p->kind == 1) {
+    const size_t mbytes = (size_t)p->many.points * esize(p->dtype);
+    const char* mi = (const char*)in;
+    const char* mo = (const char*)out;
+    if (in != out && mi < mo + mbytes && mo < mi + mbytes) return FFT_ERR_INPLACE;
     if (p->many.has_split && in == out) return FFT_ERR_INPLACE;
     hipEvent_t* slot = prof_slot(p, s);
     if (slot) hipEventRecord(slot[0], s);

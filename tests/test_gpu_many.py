@@ -226,6 +226,9 @@ def test_many_errors(dev):
     h = capi.fft_plan_many([1 << 15, 1 << 15], capi.FFT_C64, capi.FFT_FORWARD)
     try:
         assert capi.fft_exec_status(h, xt.data_ptr(), xt.data_ptr(), 0) == capi.FFT_ERR_INPLACE
+        # partially overlapping buffers are refused before any launch
+        wide = torch.zeros((1 << 16) + 8, dtype=torch.complex64, device=dev)
+        assert capi.fft_exec_status(h, wide.data_ptr(), wide.data_ptr() + 64, 0) == capi.FFT_ERR_INPLACE
     finally:
         capi.fft_destroy(h)
     for sizes, code in (([3], capi.FFT_ERR_UNSUPPORTED_SIZE), ([1 << 25], capi.FFT_ERR_UNSUPPORTED_SIZE)):

@@ -474,3 +474,28 @@ def test_three_pass_1d_2p28_sampled(dev):
     assert worst <= tol_fp32(n)
     assert rt <= 2 * tol_fp32(n)
     assert abs(ey - ex) / ex <= 1e-5
+
+
+@pytest.mark.parametrize("n,b", [(1024, 1 << 21), (1 << 20, 1 << 11)])
+def test_batch_beyond_2p31_points(dev, n, b):
+    # 2^31 points in one plan (16 GiB each way): element offsets past the
+    # 32-bit range; sampled rows, the last included, against the oracle
+    print(f"batch of 2^31 points: n={n} batch={b}", flush=True)
+    g = torch.Generator(device=dev)
+    g.manual_seed(31)
+    xt = torch.randn(b, n, dtype=torch.complex64, device=dev, generator=g)
+    y = torch.empty_like(xt)
+    h = capi.fft_plan([n], b, 1, capi.FFT_C64, capi.FFT_FORWARD)
+    try:
+        capi.fft_exec(h, xt.data_ptr(), y.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+    finally:
+        capi.fft_destroy(h)
+    rows = torch.tensor([0, 1, b // 2 - 1, b // 2, b - 2, b - 1, 12345 % b, (b * 7) // 9], device=dev)
+    xs = xt[rows].cpu().numpy()
+    ys = y[rows].cpu().numpy()
+    del xt, y
+    torch.cuda.empty_cache()
+    err = rel_l2_rows(ys, oracle.fft(xs), n)
+    print(f"n={n} batch={b}: sampled rows rel-L2 max {err.max():.3e}")
+    assert err.max() <= tol_fp32(n), float(err.max())
