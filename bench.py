@@ -21,7 +21,9 @@ step's working set between steps: every step reads its input from HBM.
 Other modes (used to make the rocprofv3 summaries under profiles/):
   --mode profile     run warmup + steps only (no CPU baseline), for
                      `rocprofv3 --kernel-trace --stats` and `--pmc` runs;
-                     also runs one plain 256 MiB device copy (calibration).
+                     also runs one plain 256 MiB device copy (calibration);
+                     --profile-workload image2d|many profiles the 4096^2 image
+                     or the 512 uneven transforms instead of the step
   --mode configs     every benchmarked workload (1024 single, 1024 x 32768,
                      16 x 2^20 forward and inverse, the 4096^2 image, the
                      512 uneven batch in three storage types, 64 x 2^16
@@ -96,9 +98,11 @@ def parse_args(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("DIR_FETCH", "DIR_WRITE"))
-    ap.add_argument("--profile-workload", choices=["step", "image2d"], default="step",
-                    help="profile mode: the benchmarked step, or the 4096x4096 2-D image forward "
-                         "transform (tuned schedule, four rotating buffers)")
+    ap.add_argument("--profile-workload", choices=["step", "image2d", "many"], default="step",
+                    help="profile mode: the benchmarked step, the 4096x4096 2-D image forward "
+                         "transform (tuned schedule, four rotating buffers), or the 512 uneven "
+                         "complex64 transforms in one persistent launch (tuned schedule, rotating "
+                         "buffers of >= 1 GiB)")
     return ap.parse_args(argv)
 
 
@@ -580,7 +584,7 @@ def main(argv=None) -> int:
         capi.fft_exec(fwd, xi.data_ptr(), yi.data_ptr(), stream)
         capi.fft_exec(inv, yi.data_ptr(), zi.data_ptr(), stream)
 
-    image_only = args.mode == "profile" and args.profile_workload == "image2d"
+    image_only = args.mode == "profile" and args.profile_workload in ("image2d", "many")
     for i in range(0 if image_only else args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -615,6 +619,22 @@ def main(argv=None) -> int:
             torch.cuda.synchronize()
             capi.fft_destroy(h2)
             del imgs
+        elif args.profile_workload == "many":
+            del sets
+            torch.cuda.empty_cache()
+            sizes = [int(v) for v in workloads.uneven_sizes(512, 8, 16, seed=3)]
+            hm = capi.fft_plan_many_ex(sizes, capi.FFT_C64, capi.FFT_FORWARD,
+                                       autotune.many_schedule_for(sizes, capi.FFT_C64))
+            pts = sum(sizes)
+            nm = max(2, math.ceil(ROT_BYTES / (16 * pts)))
+            bufs = [(torch.randn(pts, dtype=torch.complex64, device=dev),
+                     torch.empty(pts, dtype=torch.complex64, device=dev)) for _ in range(nm)]
+            for i in range(args.warmup + args.steps):
+                xi, yi = bufs[i % nm]
+                capi.fft_exec(hm, xi.data_ptr(), yi.data_ptr(), stream)
+            torch.cuda.synchronize()
+            capi.fft_destroy(hm)
+            del bufs
         else:
             for i in range(args.steps):
                 step(i)
