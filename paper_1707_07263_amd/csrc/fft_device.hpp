@@ -161,6 +161,23 @@ __device__ __forceinline__ float2 load_c(const c16bf* p) {
   c16bf v = *p;
   return make_float2(bf16_to_f32(v.x), bf16_to_f32(v.y));
 }
+// A complex64 point of a strided (column) pass, which reads every point
+// once: loaded with the nontemporal hint, so that the caches favour the
+// pass's output, which the next pass reads, over its input (measured on the
+// two-pass 2^20 split: both passes of both directions got faster).  Only
+// where a strip's row segment covers whole 128 B lines (16 or more columns):
+// narrower strips share each line with the neighbouring strip, which then
+// finds it evicted and fetches it again (the 8-column 2-D column pass got
+// a third slower).
+template <int LOADM, int W, typename TS>
+__host__ __device__ constexpr bool kStreamLoads() {
+  return LOADM == 1 && sizeof(TS) == 8 && W * sizeof(TS) >= 128;
+}
+__device__ __forceinline__ float2 load_stream(const float2* p) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  const f2v r = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+  return make_float2(r.x, r.y);
+}
 __device__ __forceinline__ void store_c(float2* p, float2 v) { *p = v; }
 __device__ __forceinline__ void store_c(__half2* p, float2 v) {
   *p = __halves2half2(__float2half_rn(v.x), __float2half_rn(v.y));
@@ -435,7 +452,10 @@ k_strip(PassArgs a) {
     const uint32_t sgn = a.conj_in ? 0x80000000u : 0u;
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
-      v[q] = load_c(src + q * step);
+      if constexpr (kStreamLoads<LOADM, W, TS>())
+        v[q] = load_stream(reinterpret_cast<const float2*>(src + q * step));
+      else
+        v[q] = load_c(src + q * step);
       v[q].y = __uint_as_float(__float_as_uint(v[q].y) ^ sgn);
     }
   }
@@ -539,7 +559,9 @@ k_pipe(PassArgs a) {
     const int64_t step = (int64_t)T * a.in_elem;
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
-      if constexpr (sizeof(TS) == 8)
+      if constexpr (kStreamLoads<LOADM, W, TS>())
+        vn[q] = load_stream(reinterpret_cast<const float2*>(src + q * step));
+      else if constexpr (sizeof(TS) == 8)
         vn[q] = load_c(src + q * step);
       else
         vn[q] = src[q * step];
