@@ -245,7 +245,20 @@ def cpu_baseline(x_np, seconds: float):
     oracle.set_threads(cores)
     out["single_thread"] = {"value": round(reps1 * 2 * 5.0 * N * math.log2(N) / el1 / 1e9, 3),
                             "sample": f"{reps1} x (forward + inverse of one 2^20 transform) in {el1:.1f} s"}
+    out["cpu_model"] = cpu_model()
     return out
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _stats(v):

@@ -137,3 +137,8 @@ def test_stats_helper():
     s = bench._stats([3.0, 1.0, 2.0, 10.0])
     assert s == {"min": 1.0, "median": 2.0, "p90": 10.0}
     assert bench._stats([5.0]) == {"min": 5.0, "median": 5.0, "p90": 5.0}
+
+
+def test_cpu_model_names_the_host():
+    name = bench.cpu_model()
+    assert isinstance(name, str) and name
