@@ -97,8 +97,8 @@ int fft_plan(const int64_t *n, int64_t batch, int dims, int dtype, int direction
  *             | 'xcd=' digits         (one '0'/'1' for every pass, or one digit
  *                                       per pass, first pass first; 1: consecutive
  *                                       tiles run on one XCD, sharing its L2.
- *                                       Persistent variants ('q') walk their tiles
- *                                       round-robin and ignore the digit)
+ *                                       Persistent variants ('q'): the workgroups
+ *                                       of one XCD start on consecutive tiles)
  *             | 'col3=' 0|1           (2-D: columns as two sub-passes of sqrt(rows)
  *                                       points; rows a power of 4, at least 2 columns)
  *             | 'colt=' variant       (the first of those sub-passes)

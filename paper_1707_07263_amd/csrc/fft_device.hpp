@@ -579,7 +579,10 @@ k_pipe(PassArgs a) {
   };
   static_assert(!TWID || W * PP <= NT, "one step-row entry per lane");
 
-  int64_t tile = blockIdx.x;
+  // with the XCD remap, the workgroups of one XCD start on consecutive
+  // tiles, so that neighbouring strips, which share cache lines when a row
+  // segment is narrower than a line, are in flight on one L2 together
+  int64_t tile = tile_of(blockIdx.x, gridDim.x, a.xcd_remap);
   if (tile < a.total_tiles) prefetch(tile);
   lds_barrier();  // stage twiddles visible
   for (; tile < a.total_tiles; tile += gridDim.x) {

@@ -309,7 +309,8 @@ PERSISTENT = sorted(n for n in _variant_names(lambda s: "q" in s.split("_")[0] a
 @pytest.mark.parametrize("name", PERSISTENT)
 def test_persistent_variants(dev, name):
     # every persistent (software-pipelined) variant through a plan that uses
-    # it, with more tiles than resident workgroups and a ragged last tile
+    # it, with more tiles than resident workgroups and a ragged last tile;
+    # the inverse with the XCD remap (permuted start tiles)
     from paper_1707_07263_amd import capi as c
     i = [c.fft_variant_name(k) for k in range(c.fft_variant_count())].index(name)
     d = c.fft_variant_describe(i)
@@ -322,7 +323,7 @@ def test_persistent_variants(dev, name):
         n, batch, sched = 512 * L, 5, f"split=512;b={name}"
     x = workloads.normal_batch(n, batch, seed=L + batch)
     check_1d(x, n, False, dev, schedule=sched)
-    check_1d(x, n, True, dev, schedule=sched)
+    check_1d(x, n, True, dev, schedule=sched + ";xcd=1")
 
 
 THREE_PASS_SHAPES = [(16, 64), (16, 1024), (64, 16), (256, 512), (1024, 16), (1024, 64), (4096, 8),

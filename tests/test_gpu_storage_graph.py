@@ -199,8 +199,8 @@ def _variants_16(kind):
 @pytest.mark.parametrize("name", _variants_16("f16") + _variants_16("bf16"))
 def test_16bit_persistent_variants(dev, name):
     # every persistent 16-bit variant through a plan that uses it (more tiles
-    # than resident workgroups), forward and inverse, against the oracle on
-    # the quantised input
+    # than resident workgroups), forward and inverse (the inverse with the
+    # XCD remap), against the oracle on the quantised input
     tname = "float16" if name.endswith("_f16") else "bfloat16"
     code = capi.FFT_C16F if tname == "float16" else capi.FFT_C16BF
     tdt = getattr(torch, tname)
@@ -217,7 +217,8 @@ def test_16bit_persistent_variants(dev, name):
     xt = to_gpu_16(x, dev, tdt)
     st = torch.cuda.current_stream().cuda_stream
     for direction in (capi.FFT_FORWARD, capi.FFT_INVERSE):
-        h = capi.fft_plan_ex([n], b, 1, code, direction, sched)
+        h = capi.fft_plan_ex([n], b, 1, code, direction,
+                             sched + (";xcd=1" if direction == capi.FFT_INVERSE else ""))
         try:
             y = torch.empty_like(xt)
             capi.fft_exec(h, xt.data_ptr(), y.data_ptr(), st)
