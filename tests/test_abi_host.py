@@ -222,3 +222,30 @@ def test_pipe_argument_errors(lib):
     assert lib.fft_pipe_exec(None, None, None, 1) == capi.FFT_ERR_INVALID_ARGUMENT
     assert lib.fft_pipe_wait(None) == capi.FFT_ERR_INVALID_ARGUMENT
     assert lib.fft_pipe_destroy(None) == capi.FFT_OK
+
+
+def test_tuned_cache_is_valid_for_the_compiled_variants(lib):
+    # every committed tuned schedule plans on the host, and the passes it
+    # names are the passes the planner builds (no GPU needed)
+    import json
+    from paper_1707_07263_amd import autotune, workloads
+    with open(autotune.CACHE_PATH) as f:
+        cache = json.load(f)
+    uneven = [int(s) for s in workloads.uneven_sizes(512, 8, 16, seed=3)]
+    plans = many = 0
+    for key, entry in cache.items():
+        arch, kind, shape, batch, dtype = key.split("|")
+        sched = entry["schedule"]
+        if kind == "plan":
+            dims = [int(v) for v in shape.split("x")]
+            d = capi.fft_describe(dims, int(batch), len(dims), int(dtype), sched)
+            named = [v.split("=", 1)[1] for v in sched.split(";")
+                     if v.split("=", 1)[0] in ("single", "a", "b", "row", "col", "colt")]
+            assert set(named) <= set(d["names"]), (key, named, d["names"])
+            plans += 1
+        else:
+            assert kind == "many" and autotune._many_key(uneven, int(dtype)) == key, key
+            items, _, _ = capi.fft_describe_many(uneven, int(dtype), sched)
+            assert len(items) > 0
+            many += 1
+    assert plans >= 8 and many == 3
