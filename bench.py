@@ -37,6 +37,7 @@ Other modes (used to make the rocprofv3 summaries under profiles/):
                      passes, forward 16 x 2^20, one JSON line
   --summarize-trace DIR         print the kernel-time summary of a trace run
   --summarize-pmc DIR_FETCH DIR_WRITE  print per-kernel HBM traffic
+  --summarize-counters DIR      print per-kernel averages of any counters
 """
 from __future__ import annotations
 
@@ -98,6 +99,7 @@ def parse_args(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("DIR_FETCH", "DIR_WRITE"))
+    ap.add_argument("--summarize-counters", metavar="DIR")
     ap.add_argument("--profile-workload", choices=["step", "image2d", "many"], default="step",
                     help="profile mode: the benchmarked step, the 4096x4096 2-D image forward "
                          "transform (tuned schedule, four rotating buffers), or the 512 uneven "
@@ -174,6 +176,24 @@ def summarize_pmc(dfetch: str, dwrite: str) -> str:
         aw = sum(w) / len(w)
         lines.append(f"kernel={k} dispatches={len(f)} fetch_kib_avg={af:.1f} write_kib_avg={aw:.1f} "
                      f"hbm_bytes_per_launch={(af * cf + aw * cw) * 1024:.0f}")
+    return "\n".join(lines)
+
+
+def summarize_counters(d: str) -> str:
+    """Per-kernel average of every counter in a `rocprofv3 --pmc` run."""
+    rows = _csv_rows(d, "counter_collection.csv")
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    per = {}
+    for r in rows:
+        k = _short(r["Kernel_Name"])
+        per.setdefault(k, {}).setdefault(r["Counter_Name"].strip(), []).append(float(r["Counter_Value"]))
+    lines = []
+    for k in sorted(per):
+        cs = per[k]
+        n = max(len(v) for v in cs.values())
+        vals = " ".join(f"{c}={sum(v) / len(v):.0f}" for c, v in sorted(cs.items()))
+        lines.append(f"kernel={k} dispatches={n} {vals}")
     return "\n".join(lines)
 
 
@@ -559,6 +579,9 @@ def main(argv=None) -> int:
         return 0
     if args.summarize_pmc:
         print(summarize_pmc(*args.summarize_pmc))
+        return 0
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters))
         return 0
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU; --gpus N > 1 is not supported. The batch of "

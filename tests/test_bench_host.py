@@ -142,3 +142,17 @@ def test_stats_helper():
 def test_cpu_model_names_the_host():
     name = bench.cpu_model()
     assert isinstance(name, str) and name
+
+
+def test_summarize_counters_averages_per_kernel(tmp_path):
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    _write_csv(str(tmp_path / "c" / "run_counter_collection.csv"), hdr, [
+        [PIPE_A, "SQ_LDS_BANK_CONFLICT", 10], [PIPE_A, "SQ_LDS_BANK_CONFLICT", 30],
+        [PIPE_A, "SQ_INSTS_LDS", 100], [PIPE_A, "SQ_INSTS_LDS", 100], [COPY, "SQ_INSTS_LDS", 0],
+    ])
+    out = bench.summarize_counters(str(tmp_path)).splitlines()
+    line = [l for l in out if PIPE_A in l][0]
+    assert "dispatches=2" in line and "SQ_LDS_BANK_CONFLICT=20" in line and "SQ_INSTS_LDS=100" in line
+    assert any(COPY in l and "SQ_INSTS_LDS=0" in l for l in out)
+    with pytest.raises(SystemExit):
+        bench.summarize_counters(str(tmp_path / "none"))
