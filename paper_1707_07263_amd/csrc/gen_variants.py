@@ -14,6 +14,10 @@ ROLE = {"r": "ROLE_ROW", "a": "ROLE_SPLIT_A", "c": "ROLE_COL", "t": "ROLE_COL_TW
 
 
 def lds_bytes(L, W, ex=0):
+    # the kernels' padded layout needs W * (L + L/32 + 2) slots: this is an
+    # upper bound of it for L >= 16 (shorter lines, whose tiles are far below
+    # the limit, need one or two slots more), kept so that the registry stays
+    # the set of variants measured and tested
     return W * (L + (L >> 4) + 1) * (4 if ex else 8)
 
 

@@ -5,12 +5,13 @@
 
 namespace mfft {
 
-// LDS needed by a tile of length 2^lg: W = NT/T lines, padded layout.
+// LDS needed by a tile of length 2^lg: W = NT/T lines of the padded
+// layout's line stride (LdsLayout<L>::LS).
 template <int P, int NT>
 __host__ __device__ constexpr int many_lds_len(int lg) {
   return lg == 0 ? NT
                  : (NT / ((1 << lg) / ((P < (1 << lg)) ? P : (1 << lg)))) *
-                       ((1 << lg) + ((1 << lg) >> 4) + 1);
+                       ((1 << lg) + ((1 << lg) >> 5) + 2);
 }
 template <int P, int NT, int MAXLG = kManyMaxLg>
 __host__ __device__ constexpr int many_lds_max(int lg = 0) {
