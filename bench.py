@@ -96,6 +96,9 @@ def parse_args(argv=None):
     ap.add_argument("--mode", choices=["bench", "profile", "ablation", "configs", "transfer"],
                     default="bench")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the other forms (2-D image, uneven batch in three storage types, "
+                         "forward + adjoint pair) after the headline step")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("DIR_FETCH", "DIR_WRITE"))
@@ -234,10 +237,25 @@ def read_traffic(kernel_name: str):
 # ---------------------------------------------------------------------------
 # GPU benchmark
 # ---------------------------------------------------------------------------
+def timing_oracle():
+    """The oracle built for this host's CPU (gcc -O3 -march=native, in a
+    temporary directory, removed once loaded), or the portable in-tree build
+    if that compile fails.  Returns (oracle functions, build description)."""
+    import tempfile
+
+    import oracle as portable
+    try:
+        with tempfile.TemporaryDirectory(prefix="oracle_native_") as d:
+            return portable.native(d), "gcc -O3 -march=native -fopenmp"
+    except Exception as e:  # no compiler on this host: the portable build
+        print(f"[bench] native oracle build failed ({e}); timing the portable build", file=sys.stderr)
+        return portable, "gcc -O3 -fopenmp (portable)"
+
+
 def cpu_baseline(x_np, seconds: float):
     """FP64 oracle on the host cores: forward + inverse of the same 16 x 2^20
     batch, repeated until `seconds` have passed (at least once)."""
-    import oracle
+    oracle, build = timing_oracle()
     cores = len(os.sched_getaffinity(0))
     oracle.set_threads(cores)
     reps, t0 = 0, time.perf_counter()
@@ -266,6 +284,7 @@ def cpu_baseline(x_np, seconds: float):
     out["single_thread"] = {"value": round(reps1 * 2 * 5.0 * N * math.log2(N) / el1 / 1e9, 3),
                             "sample": f"{reps1} x (forward + inverse of one 2^20 transform) in {el1:.1f} s"}
     out["cpu_model"] = cpu_model()
+    out["build"] = build
     return out
 
 
@@ -423,6 +442,131 @@ def configs_report(capi, torch, reps):
     add("64 x 2^16 forward + adjoint backward (autograd pair)",
         [plan([1 << 16], 64, C64, capi.FFT_FORWARD), plan([1 << 16], 64, C64, capi.FFT_INVERSE, 1.0)], 8,
         vendor=(lambda x: tf.ifft(tf.fft(x), norm="forward"), [(64, 1 << 16)], "ifft(fft(x), norm=forward)"))
+    return out
+
+
+def _rel_l2(got, ref):
+    """||got - ref|| / ||ref|| in FP64 (an exactly zero reference needs a zero output)."""
+    import numpy as np
+    g = np.asarray(got, dtype=np.complex128).reshape(-1)
+    r = np.asarray(ref, dtype=np.complex128).reshape(-1)
+    nr = np.linalg.norm(r)
+    return float(np.linalg.norm(g - r) / nr) if nr > 0 else float(np.linalg.norm(g))
+
+
+def _to_c128(t):
+    """A device tensor of complex64, or of 16-bit pairs [..., 2], as numpy complex128."""
+    import numpy as np
+    import torch
+    a = t.detach().cpu()
+    if a.dtype in (torch.float16, torch.bfloat16):
+        f = a.float().numpy()
+        return f[..., 0].astype(np.float64) + 1j * f[..., 1].astype(np.float64)
+    return a.numpy().astype(np.complex128)
+
+
+def forms_report(capi, torch, reps):
+    """Every form of the method beside the headline step, each on its own
+    workload: device time (per-launch HIP events over rotating buffers of
+    >= 1 GiB), method bytes and fraction of peak HBM, and the error of the
+    same plan's output against the FP64 oracle on that workload's seeded
+    input (per length for the uneven batch).  The oracle runs after the GPU
+    timing, on the host."""
+    import numpy as np
+
+    import oracle
+    from paper_1707_07263_amd import autotune, workloads
+    C64, F16, BF16 = capi.FFT_C64, capi.FFT_C16F, capi.FFT_C16BF
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream().cuda_stream
+    out = {}
+
+    def rate(plans, nbytes_io):
+        us, per_rep = _time_plans(capi, torch, plans, nbytes_io, reps)
+        moved = sum(sum(capi.fft_plan_info(h)["bytes_pass"]) for h, _ in plans)
+        flops = sum(capi.fft_plan_info(h)["flops"] for h, _ in plans)
+        return {"us": round(us, 2), "us_reps": _stats(per_rep),
+                "GFLOPs": round(flops / (us * 1e-6) / 1e9, 1),
+                "method_bytes": moved, "method_GBps": round(moved / (us * 1e-6) / 1e9, 1),
+                "frac_of_peak": round(moved / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+                "kernels": [capi.fft_plan_info(h)["pass_variant"] for h, _ in plans]}
+
+    def run(h, x):
+        y = torch.empty_like(x)
+        capi.fft_exec(h, x.data_ptr(), y.data_ptr(), st)
+        torch.cuda.synchronize()
+        return y
+
+    # the 4096 x 4096 image, rows then columns (Sec. 2.3.2)
+    shape = [4096, 4096]
+    h = capi.fft_plan_ex(shape, 1, 2, C64, capi.FFT_FORWARD, autotune.schedule_for(shape, 1, C64))
+    z = workloads.speckle_image(4096, 4096, seed=2).astype(np.complex64)
+    got = _to_c128(run(h, torch.from_numpy(z).to(dev)))
+    r = rate([(h, z.nbytes)], 2 * z.nbytes)
+    capi.fft_destroy(h)
+    r["rel_l2_vs_oracle"] = _rel_l2(got, oracle.fft2(z))
+    r["tolerance"] = 2.4e-5
+    out["image_4096x4096_c64"] = r
+    print(f"[bench] form image 4096^2: {r['us']} us, rel-L2 {r['rel_l2_vs_oracle']:.2e}",
+          file=sys.stderr, flush=True)
+
+    # 512 uneven lengths 2^8..2^16 in one launch, three storage types
+    sizes, packed = workloads.uneven_batch(512, 8, 16, seed=3)
+    sl = [int(v) for v in sizes]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    for dt, name, tol in ((C64, "c64", None), (F16, "f16", 1e-3), (BF16, "bf16", 8e-3)):
+        h = capi.fft_plan_many_ex(sl, dt, capi.FFT_FORWARD, autotune.many_schedule_for(sl, dt))
+        if dt == C64:
+            xin = packed.astype(np.complex64)
+            xt = torch.from_numpy(xin).to(dev)
+        else:
+            tdt = torch.float16 if dt == F16 else torch.bfloat16
+            pairs = np.stack([packed.real, packed.imag], -1).astype(np.float32)
+            xt = torch.from_numpy(pairs).to(tdt).to(dev)
+            xin = _to_c128(xt)  # the values the GPU holds: the oracle's input
+        got = _to_c128(run(h, xt))
+        wd = capi.fft_many_watchdog(h, 1)
+        esz = 8 if dt == C64 else 4
+        r = rate([(h, sum(sl) * esz)], 2 * sum(sl) * esz)
+        capi.fft_destroy(h)
+        ref = oracle.fft_many(xin, sizes)
+        per = {}
+        for lg in range(8, 17):
+            sel = [i for i in range(len(sl)) if sl[i] == 1 << lg]
+            if sel:
+                per[f"2^{lg}"] = max(_rel_l2(got[off[i]:off[i + 1]], ref[off[i]:off[i + 1]]) for i in sel)
+        r["rel_l2_vs_oracle_max_per_length"] = per
+        r["rel_l2_vs_oracle_max"] = max(per.values())
+        r["tolerance"] = "1e-6*log2(N) per transform" if tol is None else tol
+        r["watchdog"] = "ok" if wd == capi.FFT_OK else "expired"
+        r["points"] = sum(sl)
+        out[f"uneven512_{name}"] = r
+        print(f"[bench] form 512 uneven {name}: {r['us']} us, max rel-L2 {r['rel_l2_vs_oracle_max']:.2e}",
+              file=sys.stderr, flush=True)
+
+    # differentiable pair: 64 x 2^16 forward, then the adjoint (inverse
+    # direction, scale 1) of g = 2 W^2 (F x), the gradient of sum |W F x|^2
+    x, w, _ = workloads.autograd_case(64, 1 << 16, seed=4)
+    x64 = x.astype(np.complex64)
+    hf = capi.fft_plan_ex([1 << 16], 64, 1, C64, capi.FFT_FORWARD, autotune.schedule_for([1 << 16], 64, C64))
+    ha = capi.fft_plan_ex([1 << 16], 64, 1, C64, capi.FFT_INVERSE, autotune.schedule_for([1 << 16], 64, C64))
+    capi.fft_set_scale(ha, 1.0)
+    y = run(hf, torch.from_numpy(x64).to(dev))
+    g = (2.0 * torch.from_numpy(w.astype(np.float32)).to(dev) ** 2) * y
+    grad = _to_c128(run(ha, g))
+    yc = _to_c128(y)
+    nb = x64.nbytes
+    r = rate([(hf, nb), (ha, nb)], 4 * nb)
+    capi.fft_destroy(hf)
+    capi.fft_destroy(ha)
+    ref_y = oracle.fft(x64)
+    r["rel_l2_forward_vs_oracle"] = _rel_l2(yc, ref_y)
+    r["rel_l2_gradient_vs_oracle"] = _rel_l2(grad, oracle.adjoint(2.0 * w ** 2 * ref_y))
+    r["tolerance"] = {"forward": 1.6e-5, "gradient": 5e-5}
+    out["autograd_64x2^16_fwd_adjoint"] = r
+    print(f"[bench] form 64 x 2^16 forward + adjoint: {r['us']} us, forward rel-L2 "
+          f"{r['rel_l2_forward_vs_oracle']:.2e}, gradient {r['rel_l2_gradient_vs_oracle']:.2e}",
+          file=sys.stderr, flush=True)
     return out
 
 
@@ -722,6 +866,8 @@ def main(argv=None) -> int:
     # round trip of the last step's buffers as a sanity check
     xi, yi, zi = sets[(args.warmup + args.steps - 1) % nsets]
     rt = (torch.linalg.vector_norm(zi - xi) / torch.linalg.vector_norm(xi)).item()
+    y_gpu = yi.cpu().numpy()
+    z_gpu = zi.cpu().numpy()
 
     flops_step = info_f["flops"] + info_i["flops"]
     value = flops_step / (ms_per_step * 1e-3) / 1e9
@@ -759,6 +905,19 @@ def main(argv=None) -> int:
     capi.fft_destroy(inv)
     del sets
     torch.cuda.empty_cache()
+    # error of the step's results against the FP64 oracle: the forward output
+    # against eq. 1 of the input, the inverse output against eq. 2 of the GPU
+    # forward output (per transform; the batch maximum)
+    import oracle
+    ref_y = oracle.fft(x_np)
+    ref_z = oracle.fft(y_gpu, inverse=True)
+    result["config"]["rel_l2_vs_oracle"] = {
+        "forward_max": max(_rel_l2(y_gpu[b], ref_y[b]) for b in range(BATCH)),
+        "inverse_max": max(_rel_l2(z_gpu[b], ref_z[b]) for b in range(BATCH)),
+        "tolerance": 2.0e-5}
+    del ref_y, ref_z
+    if not args.no_forms:
+        result["forms"] = forms_report(capi, torch, max(10, min(args.steps, 20)))
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(x_np, args.cpu_seconds)

@@ -61,7 +61,8 @@ typedef struct fft_plan_s *fft_plan_t;
 #define FFT_OK 0
 #define FFT_ERR_INVALID_ARGUMENT (-1) /* null pointer, dims, batch, dtype, direction, schedule */
 #define FFT_ERR_UNSUPPORTED_SIZE (-2) /* a length that is not a power of two, or out of range */
-#define FFT_ERR_ALIGNMENT (-3)        /* in/out not aligned to the element size */
+#define FFT_ERR_ALIGNMENT (-3)        /* in/out not aligned to the element size (8 B complex64,
+                                         4 B 16-bit pairs: every access moves one element) */
 #define FFT_ERR_INPLACE (-4)          /* in == out on a multi-pass plan with no workspace */
 #define FFT_ERR_HIP (-5)              /* a HIP call failed; see fft_last_hip_error() */
 #define FFT_ERR_NO_MEMORY (-6)        /* host or device allocation failed */
@@ -73,6 +74,9 @@ typedef struct fft_plan_s *fft_plan_t;
 #define FFT_MAX_LOG2_2D 14
 
 /*
+ * Plan (Sec. 2.3.2: how many kernel calls a length needs, and the N = N1*N2
+ * split of eq. 5 between them; Sec. 2.3.1: the sin/cos table built before
+ * the transform).
  * Create a plan for `batch` transforms of shape n[0..dims) (dims 1 or 2;
  * for dims 2, n[0] = rows, n[1] = columns, row-major), element type `dtype`
  * and `direction`.  Builds the twiddle tables (float64 -> float32 on the
@@ -180,6 +184,8 @@ int fft_many_watchdog(fft_plan_t plan, int clear);
 int fft_many_set_wait_limit(fft_plan_t plan, int64_t microseconds);
 
 /*
+ * Execute (eq. 1 forward or eq. 2 inverse on every transform of the plan, by
+ * the passes of Sec. 2.3.2; for 2-D, rows then columns).
  * Queue the transform on `stream`.  Asynchronous: no host synchronisation, no
  * allocation, no host reads of device data, so it may be captured into a
  * hipGraph.  `in` and `out` must not partially overlap; in == out is allowed
@@ -194,6 +200,7 @@ int fft_many_set_wait_limit(fft_plan_t plan, int64_t microseconds);
 int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
 
 /*
+ * Output scale (eq. 2 carries 1/N; eq. 1 none).
  * Scale applied to every output value (default 1 forward, 1/(product of
  * lengths) inverse, per transform for plan_many).  The adjoint of the forward
  * transform is the inverse-direction plan with scale 1.
@@ -201,6 +208,7 @@ int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
 int fft_set_scale(fft_plan_t plan, double scale);
 
 /*
+ * Workspace for the global-memory exchanges between passes (Sec. 2.3.2/2.3.3).
  * Device scratch a plan needs to run in place (1-D two-pass), on every exec
  * (1-D three-pass plans, lengths above 2^24: one buffer of batch * N
  * elements, allocated by the plan) or, for plan_many, for its queue and
@@ -225,6 +233,8 @@ typedef struct {
   int gpu_twiddles;      /* 1 if the tables were generated on the GPU */
 } fft_plan_info_t;
 
+/* What a plan runs (the passes of Sec. 2.3.2 and the nominal work of eq. 1
+ * counted as 5 N log2 N).  FFT_ERR_INVALID_ARGUMENT for NULL arguments. */
 int fft_plan_info(fft_plan_t plan, fft_plan_info_t *info);
 
 /* Free the plan's tables and workspace.  NULL is a no-op. */

@@ -23,18 +23,29 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+_FLAGS = ["-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-fno-fast-math", "-ffp-contract=off"]
+
+
 def build(force: bool = False) -> str:
-    """Compile oracle.c into liboracle.so with gcc (FP64, no fast-math)."""
+    """Compile oracle.c into liboracle.so with gcc (FP64, no fast-math, no
+    FMA contraction).  The in-tree library is built for any x86-64 host, since
+    it may run on another machine than the one that built it."""
     if force or not os.path.exists(_LIB_PATH) or (
         os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)
     ):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(
-            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-             "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"]
-        )
+        subprocess.check_call(["gcc"] + _FLAGS + [_SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def native(directory: str) -> "Oracle":
+    """The oracle compiled for the CPU it runs on (-march=native), into
+    `directory`, for timing the CPU baseline on that host.  Same source,
+    same FP64 arithmetic without fast-math or FMA contraction."""
+    path = os.path.join(directory, "liboracle_native.so")
+    subprocess.check_call(["gcc", "-march=native"] + _FLAGS + [_SRC, "-o", path, "-lm"])
+    return Oracle(path)
 
 
 def _declare(lib):
@@ -199,3 +210,9 @@ class Oracle:
 
     def dft_at(self, *a, **k):
         return self._swap(dft_at, *a, **k)
+
+    def max_threads(self):
+        return self._swap(max_threads)
+
+    def set_threads(self, n):
+        return self._swap(set_threads, n)

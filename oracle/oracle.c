@@ -264,7 +264,6 @@ int oracle_dft_direct(const double *in, double *out, int64_t n, int sign) {
   return 0;
 }
 
-/* Threads an OpenMP parallel region of this library would use. */
 /*
  * Outputs X[ks[i]] of eq. 1 (sign -1) or eq. 2 (sign +1), each
  * sum_t x[t] W_N^{sign * t k}, times `scale` (negative: 1 forward, 1/N

@@ -169,6 +169,8 @@ def fft_many(packed: torch.Tensor, sizes, inverse: bool = False, *, scale=None,
                          device=packed.device)
     if out is None:
         out = torch.empty_like(packed)
+    elif out.shape != packed.shape or out.dtype != packed.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous tensor of the packed input's shape and dtype")
     plan.exec(packed, out)
     return out
 
