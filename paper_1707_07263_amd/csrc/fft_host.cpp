@@ -65,14 +65,21 @@ const Variant* find_by_name(const std::string& name) {
   return nullptr;
 }
 
-// Best variant of a role/length/dtype: prefer P = 16, then the W closest to
-// `want_w` from below (never more lines than there are to transform, when
-// some variant allows that), then the thread count closest to 256.
+// Best variant of a role/length/dtype: never more lines per tile than there
+// are to transform when some variant allows that (a hard filter: a tile
+// wider than the lines would compute and drop whole lines, and plans whose
+// tiles must cover their lines exactly refuse it); among those prefer
+// P = 16, then the W closest to `want_w` from below, then the thread count
+// closest to 256.
 const Variant* pick(int role, int L, int dtype, int want_w, int64_t lines) {
+  bool some_fit = false;
+  for (const Variant& v : variants())
+    if (v.role == role && v.L == L && v.dtype == dtype && v.W <= lines) some_fit = true;
   const Variant* best = nullptr;
   double best_score = 1e300;
   for (const Variant& v : variants()) {
     if (v.role != role || v.L != L || v.dtype != dtype) continue;
+    if (some_fit && v.W > lines) continue;
     double score = 0;
     score += (v.P == 16 || v.P == v.L) ? 0 : 1000;
     const int w_cap = (int)std::max<int64_t>(1, std::min<int64_t>(want_w, lines));

@@ -188,6 +188,11 @@ def pipe_set():
     return out
 
 
+# check mode: emit() records the files whose committed text differs from what
+# the registry generates instead of writing them
+_CHECK = None
+
+
 def emit(fname, func, items):
     lines = ['#include "variants.hpp"', "", "namespace mfft {", "",
              f"void {func}(void (*add)(const Variant&)) {{"]
@@ -200,8 +205,23 @@ def emit(fname, func, items):
     text = "\n".join(lines)
     path = os.path.join(HERE, fname)
     if not os.path.exists(path) or open(path).read() != text:
+        if _CHECK is not None:
+            _CHECK.append(fname)
+            return
         with open(path, "w") as f:
             f.write(text)
+
+
+def check():
+    """Names of the committed variants_*.hip files that differ from what the
+    registry below generates (empty when they match); writes nothing."""
+    global _CHECK
+    _CHECK = []
+    try:
+        main()
+        return list(_CHECK)
+    finally:
+        _CHECK = None
 
 
 def main():

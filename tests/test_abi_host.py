@@ -172,6 +172,11 @@ def test_describe_three_pass_2d(lib):
         assert capi.fft_describe(shape, 1, 2, capi.FFT_C64)["passes"] <= 2
     # a row variant with an odd number of rows per tile cannot pair rows
     assert capi.fft_describe([4096, 4096], 1, 2, capi.FFT_C64, "row=r4096p16w1q_c64")["passes"] == 2
+    # a column tile never takes more columns than the image has when a
+    # narrower variant exists (8 columns: 8-column tiles, not 16)
+    d = capi.fft_describe([4096, 8], 2, 2, capi.FFT_C64, "col3=1")
+    assert d["passes"] == 3
+    assert all(int(nm.split("w")[1].rstrip("qx_c64")) <= 8 for nm in d["names"][:2]), d["names"]
 
 
 def test_describe_levels_method(lib):
@@ -249,3 +254,15 @@ def test_tuned_cache_is_valid_for_the_compiled_variants(lib):
             assert len(items) > 0
             many += 1
     assert plans >= 8 and many == 3
+
+
+def test_committed_variant_sources_match_generator():
+    # the variants_*.hip instantiation tables are generated from the registry
+    # in gen_variants.py at every build; the committed copies must be exactly
+    # what it generates
+    import importlib.util
+    path = os.path.join(ROOT, "paper_1707_07263_amd", "csrc", "gen_variants.py")
+    spec = importlib.util.spec_from_file_location("gen_variants_check", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    assert mod.check() == []
