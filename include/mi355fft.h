@@ -67,6 +67,8 @@ typedef struct fft_plan_s *fft_plan_t;
 #define FFT_ERR_HIP (-5)              /* a HIP call failed; see fft_last_hip_error() */
 #define FFT_ERR_NO_MEMORY (-6)        /* host or device allocation failed */
 #define FFT_ERR_WATCHDOG (-7)         /* the batched kernel's bounded wait expired */
+#define FFT_ERR_SCRATCH_LIMIT (-8)    /* fft_exec_static: the exec needs more than
+                                         FFT_STATIC_SCRATCH_BYTES of scratch */
 
 /* Size limits.  1-D lengths 1 .. 2^28 (three passes above 2^24); 2-D
  * extents 1 .. 2^14 each.  Batched plans (fft_plan_many*) take 1 .. 2^24. */
@@ -198,6 +200,35 @@ int fft_many_set_wait_limit(fft_plan_t plan, int64_t microseconds);
  * locked).
  */
 int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
+
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc).
+ * As fft_exec, except that the scratch an exec needs -- a batched plan's
+ * queue and completion counters, the intermediate of an in-place two-pass
+ * exec, or the intermediate of a three-pass plan -- is taken from one static
+ * device array of FFT_STATIC_SCRATCH_BYTES (32 MiB) that the library holds on
+ * every device it runs on until the process ends, instead of the plan's
+ * workspace.  The plan's own workspace, if any, is neither used nor changed.
+ * It calls no allocating routine: the array's device address is looked up
+ * once per device (hipGetSymbolAddress) on the first call on that device,
+ * which must be the device the plan was made on (else
+ * FFT_ERR_INVALID_ARGUMENT).  A batched plan's counters are cleared by a
+ * small fill kernel on `stream` before its launch.  Execs that need no
+ * scratch run exactly as fft_exec.  Errors: as fft_exec, plus
+ * FFT_ERR_SCRATCH_LIMIT when the exec needs more than the array holds (for
+ * complex64: in-place two-pass or three-pass execs of more than 2^22 points
+ * in all; batched plans of more than about 8 million transforms).
+ * For a batched plan the bound on its dependency waits is as in fft_exec,
+ * but the flag an expired wait sets lives in the static array, where
+ * fft_many_watchdog() does not look.
+ * Every call on one device shares that device's array and leaves its
+ * contents behind: calls that need scratch and overlap in time on one device
+ * (on different streams, or from different host threads) race and give
+ * undefined results; the caller must order them.
+ */
+#define FFT_STATIC_SCRATCH_BYTES (32u << 20)
+int fft_exec_static(fft_plan_t plan, const void *in, void *out, void *stream);
 
 /*
  * Output scale (eq. 2 carries 1/N; eq. 1 none).

@@ -26,10 +26,11 @@ FFT_ERR_INPLACE = -4
 FFT_ERR_HIP = -5
 FFT_ERR_NO_MEMORY = -6
 FFT_ERR_WATCHDOG = -7
+FFT_ERR_SCRATCH_LIMIT = -8
 
 EXPORTED = (
     "fft_plan", "fft_plan_ex", "fft_plan_many", "fft_plan_many_ex", "fft_many_watchdog",
-    "fft_many_set_wait_limit", "fft_exec", "fft_set_scale", "fft_workspace_size",
+    "fft_many_set_wait_limit", "fft_exec", "fft_exec_static", "fft_set_scale", "fft_workspace_size",
     "fft_set_workspace", "fft_plan_info", "fft_destroy", "fft_error_string",
     "fft_last_hip_error", "fft_variant_count", "fft_variant_name", "fft_variant_describe",
     "fft_describe", "fft_profile_enable", "fft_profile_sample", "fft_profile_collect", "fft_profile_read",
@@ -96,6 +97,7 @@ def load():
         "fft_many_watchdog": ([vp, ctypes.c_int], ctypes.c_int),
         "fft_many_set_wait_limit": ([vp, ctypes.c_int64], ctypes.c_int),
         "fft_exec": ([vp, vp, vp, vp], ctypes.c_int),
+        "fft_exec_static": ([vp, vp, vp, vp], ctypes.c_int),
         "fft_set_scale": ([vp, ctypes.c_double], ctypes.c_int),
         "fft_workspace_size": ([vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "fft_set_workspace": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
@@ -196,6 +198,15 @@ def fft_exec(plan: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
 def fft_exec_status(plan: int, in_ptr: int, out_ptr: int, stream: int = 0) -> int:
     """fft_exec returning the raw status (for tests of the error codes)."""
     return load().fft_exec(plan, in_ptr, out_ptr, stream)
+
+
+def fft_exec_static(plan: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    _check(load().fft_exec_static(plan, in_ptr, out_ptr, stream), "fft_exec_static")
+
+
+def fft_exec_static_status(plan: int, in_ptr: int, out_ptr: int, stream: int = 0) -> int:
+    """fft_exec_static returning the raw status (for tests of the error codes)."""
+    return load().fft_exec_static(plan, in_ptr, out_ptr, stream)
 
 
 def fft_set_scale(plan: int, scale: float) -> None:

@@ -992,19 +992,48 @@ int fft_set_workspace(fft_plan_t p, void* ptr, size_t bytes) {
   return FFT_OK;
 }
 
-int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
+namespace {
+
+// Bytes of workspace one exec of `p` with these buffers reads or writes (0:
+// none): the batched plan's queue state, the in-place two-pass intermediate,
+// or the three-pass intermediate.
+size_t exec_scratch_bytes(const fft_plan_s* p, const void* in, const void* out) {
+  if (p->kind == 1) return many_workspace_bytes(p->many);
+  if (p->kind != 0) return 0;
+  const Schedule& S = p->sched;
+  const bool ws = S.always_ws || (in == out && S.passes.size() > 1 && S.inplace_needs_ws);
+  return ws ? (size_t)S.points * esize(p->dtype) : 0;
+}
+
+__global__ void k_zero_words(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// fft_exec with the plan's workspace replaced by `ws_over` when it is not
+// NULL (the caller has checked its size); a batched plan's queue state there
+// is cleared by a fill kernel first.
+int exec_impl(fft_plan_t p, const void* in, void* out, void* stream, void* ws_over) {
   if (!p || !in || !out) return FFT_ERR_INVALID_ARGUMENT;
   if (check_ptr(in, p->dtype) || check_ptr(out, p->dtype)) return FFT_ERR_ALIGNMENT;
   hipStream_t s = (hipStream_t)stream;
+  void* const plan_ws = ws_over ? ws_over : p->ws;
   if (p->kind == 1) {
     const size_t mbytes = (size_t)p->many.points * esize(p->dtype);
     const char* mi = (const char*)in;
     const char* mo = (const char*)out;
     if (in != out && mi < mo + mbytes && mo < mi + mbytes) return FFT_ERR_INPLACE;
     if (p->many.has_split && in == out) return FFT_ERR_INPLACE;
+    if (ws_over) {
+      const int64_t words = (int64_t)(many_workspace_bytes(p->many) / sizeof(uint32_t));
+      hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 1024)), dim3(256),
+                         0, s, (uint32_t*)ws_over, words);
+      hipError_t e0 = hipGetLastError();
+      if (e0 != hipSuccess) return hip_fail(e0);
+    }
     hipEvent_t* slot = prof_slot(p, s);
     if (slot) hipEventRecord(slot[0], s);
-    hipError_t e = many_launch(p->many, in, out, p->ws, (float)p->scale, p->scale_user, p->direction > 0, s);
+    hipError_t e = many_launch(p->many, in, out, plan_ws, (float)p->scale, p->scale_user, p->direction > 0, s);
     if (slot) hipEventRecord(slot[1], s);
     if (e != hipSuccess) return hip_fail(e);
     prof_commit(p, s);
@@ -1051,10 +1080,10 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
   }
   void* ws = nullptr;
   if (same && S.passes.size() > 1 && S.inplace_needs_ws) {
-    if (!p->ws) return FFT_ERR_INPLACE;
-    ws = p->ws;
+    if (!plan_ws) return FFT_ERR_INPLACE;
+    ws = plan_ws;
   }
-  if (S.always_ws && !p->ws) return FFT_ERR_INPLACE;
+  if (S.always_ws && !plan_ws) return FFT_ERR_INPLACE;
   const bool inv = p->direction > 0;
   hipEvent_t* slot = prof_slot(p, s);
   for (size_t i = 0; i < S.passes.size(); ++i) {
@@ -1065,8 +1094,8 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
     void* src;
     void* dst;
     if (S.always_ws) {
-      src = ps.src == SEL_IN ? (void*)in : ps.src == SEL_WS ? p->ws : out;
-      dst = ps.dst == SEL_IN ? (void*)in : ps.dst == SEL_WS ? p->ws : out;
+      src = ps.src == SEL_IN ? (void*)in : ps.src == SEL_WS ? plan_ws : out;
+      dst = ps.dst == SEL_IN ? (void*)in : ps.dst == SEL_WS ? plan_ws : out;
     } else {
       src = ws ? (i == 0 ? (void*)in : ws) : (ps.src == SEL_IN ? (void*)in : out);
       dst = ws ? (i == 0 ? ws : out) : out;
@@ -1103,6 +1132,56 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
   }
   prof_commit(p, s);
   return FFT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free exec: the scratch comes from this library's own device
+// array.  Each device holds its own copy of `scratch` (at its own address)
+// from the time the library's code is loaded on it until the process ends.
+// In host code the name `scratch` is only a host-side stand-in; the device
+// address comes from hipGetSymbolAddress, looked up once per device with that
+// device current, and only that address is passed to kernels.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) unsigned char scratch[FFT_STATIC_SCRATCH_BYTES];
+
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kScratchMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev`.
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kScratchMaxDevices) return FFT_ERR_INVALID_ARGUMENT;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e);
+    if (!ptr) return FFT_ERR_INVALID_ARGUMENT;
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return FFT_OK;
+}
+
+}  // namespace
+
+int fft_exec(fft_plan_t p, const void* in, void* out, void* stream) {
+  return exec_impl(p, in, out, stream, nullptr);
+}
+
+int fft_exec_static(fft_plan_t p, const void* in, void* out, void* stream) {
+  if (!p || !in || !out) return FFT_ERR_INVALID_ARGUMENT;
+  const size_t need = exec_scratch_bytes(p, in, out);
+  if (need == 0) return exec_impl(p, in, out, stream, nullptr);
+  if (need > (size_t)FFT_STATIC_SCRATCH_BYTES) return FFT_ERR_SCRATCH_LIMIT;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev != p->device) return FFT_ERR_INVALID_ARGUMENT;
+  void* ws = nullptr;
+  const int rc = scratch_address(dev, &ws);
+  if (rc) return rc;
+  return exec_impl(p, in, out, stream, ws);
 }
 
 int fft_plan_info(fft_plan_t p, fft_plan_info_t* info) {
@@ -1181,6 +1260,7 @@ const char* fft_error_string(int status) {
     case FFT_ERR_HIP: return "HIP runtime error (see fft_last_hip_error)";
     case FFT_ERR_NO_MEMORY: return "out of memory";
     case FFT_ERR_WATCHDOG: return "batched kernel wait limit expired";
+    case FFT_ERR_SCRATCH_LIMIT: return "exec needs more scratch than the library's static array holds";
     default: return "unknown status";
   }
 }

@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_error_strings(lib):
-    for code in range(0, -8, -1):
+    for code in range(0, -9, -1):
         s = capi.error_string(code)
         assert s and s != "unknown status"
     assert capi.error_string(-99) == "unknown status"
