@@ -145,9 +145,18 @@ int fft_plan_many(const int64_t *sizes, int64_t count, int dtype, int direction,
  *   'pass2=' t         lengths of at least 2^t use two passes (1 <= t <= 1 +
  *                      log2 of the longest one-tile length, which is the default)
  *   'order=' bigfirst|given   order of the work queue
- *   'pipe=' 0|1        1: one workgroup per CU that loads its next item while
+ *   'pipe=' 0|1|2      1: one workgroup per CU that loads its next item while
  *                      it transforms the current one (compiled for p=16,
- *                      threads=512), items assigned round-robin in queue order
+ *                      threads=512), items assigned round-robin in queue order;
+ *                      2: the same pipelining in two launches per exec
+ *                      (first passes and one-pass tiles, then second passes;
+ *                      the kernel boundary orders a transform's passes, no
+ *                      workgroup waits for another), items claimed from each
+ *                      launch's atomic queue head
+ *   'pass.L=' 1|2      length 2^L in one pass or two (one needs 2^L within
+ *                      the longest tile)
+ *   'n1.L=' l          two passes for length 2^L with a first pass of 2^l
+ *                      points (both sub-lengths within the longest tile)
  *   'lag=' k           0 (default): every first-pass item ahead of every
  *                      second-pass item; k > 0: the second-pass items of the
  *                      i-th two-pass transform follow the first-pass items of
@@ -173,6 +182,17 @@ int fft_plan_many_ex(const int64_t *sizes, int64_t count, int dtype, int directi
 int fft_describe_many(const int64_t *sizes, int64_t count, int dtype, const char *schedule,
                       int32_t *items, int64_t max_items, int64_t *n_items, int32_t *first_len,
                       int32_t *first_tiles);
+
+/*
+ * Host-only: how the launches of a batched exec split fft_describe_many's
+ * item list: *n_q launches; if `q_off` is not NULL it receives n_q + 1
+ * offsets, launch p running items q_off[p] .. q_off[p+1]-1 (the two-launch
+ * kernel, schedule 'pipe=2': first passes and one-pass tiles, then second
+ * passes; the other kernels: one launch).
+ * FFT_ERR_INVALID_ARGUMENT if max_q < n_q + 1.
+ */
+int fft_describe_many_launches(const int64_t *sizes, int64_t count, int dtype, const char *schedule,
+                               int32_t *q_off, int64_t max_q, int64_t *n_q);
 
 /*
  * Batched plans only: a second-pass tile waits on its transform's counter for
@@ -220,8 +240,8 @@ int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
  * complex64: in-place two-pass or three-pass execs of more than 2^22 points
  * in all; batched plans of more than about 8 million transforms).
  * For a batched plan the bound on its dependency waits is as in fft_exec,
- * but the flag an expired wait sets lives in the static array, where
- * fft_many_watchdog() does not look.
+ * and an expired wait sets the flag in the plan's own workspace, which
+ * fft_many_watchdog() reads.
  * Every call on one device shares that device's array and leaves its
  * contents behind: calls that need scratch and overlap in time on one device
  * (on different streams, or from different host threads) race and give

@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import json
 import math
+import re
 import os
 import threading
 import time
@@ -301,19 +302,59 @@ def tune_many(sizes, dtype=capi.FFT_C64, reps=10, verbose=False):
                     for order in ("bigfirst", "given"):
                         grid.append(f"p={P};threads={threads};pass2={pass2};order={order}"
                                     + (";pipe=1" if pipe else ""))
+    # the two-launch kernel (512 lanes, tiles up to 2^12)
+    for pass2 in range(9, 14):
+        grid.append(f"p=16;threads=512;pipe=2;pass2={pass2}")
     best = None
     for s in grid:
         us = timed(s)
         if us is not None and (best is None or us < best[0]):
             best = (us, s)
-    if best is not None:
+    if best is not None and "pipe=2" not in best[1]:
         # queue order: second passes lagging the first passes by k transforms
         base = best[1]
         for lag in (1, 2, 4, 8):
             us = timed(f"{base};lag={lag}")
             if us is not None and us < best[0]:
                 best = (us, f"{base};lag={lag}")
+    if best is not None:
+        best = _tune_per_length(sizes, best, timed)
     return best[1], [best[0]]
+
+
+def _tune_per_length(sizes, best, timed):
+    """Per-length choices on top of the best global schedule: for every
+    length present, one pass or two (where both are possible) and, for two
+    passes, the first-pass length N1 (coordinate descent, two sweeps, each
+    change kept only if the whole launch gets faster)."""
+    lgs = sorted({int(math.log2(int(n))) for n in sizes}, reverse=True)
+    def opt(key, default):
+        m = re.search(r"(?:^|;)" + key + r"=(\d+)", best[1])
+        return int(m.group(1)) if m else default
+    threads, P, pipe = opt("threads", 256), opt("p", 16), opt("pipe", 0)
+    base = best[1]
+    max_tile = min(12 if (pipe != 1 or threads == 512) else 11, int(math.log2(threads * P)))
+    pass2 = opt("pass2", max_tile + 1)
+    cur = dict()
+    for _ in range(2):
+        for lg in lgs:
+            two_default = lg >= pass2 or lg > max_tile
+            options = []
+            if lg <= max_tile and lg >= 2:
+                options.append(("pass", 1 if two_default else 2))
+            for l1 in range(max(1, lg - max_tile), min(max_tile, lg - 1) + 1):
+                options.append(("n1", l1))
+            for key, val in options:
+                trial = dict(cur)
+                trial.pop(("pass", lg), None)
+                trial.pop(("n1", lg), None)
+                trial[(key, lg)] = val
+                s = base + "".join(f";{k}.{L}={v}" for (k, L), v in sorted(trial.items()))
+                us = timed(s)
+                if us is not None and us < best[0] * 0.995:
+                    best = (us, s)
+                    cur = trial
+    return best
 
 
 def tune_and_store(problems, many=(), reps=10, path=None, verbose=True):

@@ -23,6 +23,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", "-Wno-unused-value", "-I", CSRC, "-I", INCLUDE,
+    # every atomic here is issued by one lane: no wave-level combining, whose
+    # broadcast of the result would make the issuing wave wait for it at once
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
 ]
 
 

@@ -35,7 +35,7 @@ EXPORTED = (
     "fft_last_hip_error", "fft_variant_count", "fft_variant_name", "fft_variant_describe",
     "fft_describe", "fft_profile_enable", "fft_profile_sample", "fft_profile_collect", "fft_profile_read",
     "fft_twiddle_host", "fft_describe_many", "fft_pipe_create", "fft_pipe_exec", "fft_pipe_wait",
-    "fft_pipe_destroy",
+    "fft_pipe_destroy", "fft_describe_many_launches",
 )
 
 
@@ -119,6 +119,8 @@ def load():
                                ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, i64p,
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
                               ctypes.c_int),
+        "fft_describe_many_launches": ([i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_char_p,
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, i64p], ctypes.c_int),
         "fft_twiddle_host": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                               ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
         "fft_pipe_create": ([vp, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
@@ -338,3 +340,18 @@ def fft_describe_many(sizes, dtype=FFT_C64, schedule=None):
                                  items.ctypes.data_as(p32), n.value, ctypes.byref(n),
                                  fl.ctypes.data_as(p32), ft.ctypes.data_as(p32)), "fft_describe_many")
     return items, fl, ft
+
+
+def fft_describe_many_launches(sizes, dtype=FFT_C64, schedule=None):
+    """Host-only launch offsets into a batched plan's item list (n + 1 entries)."""
+    import numpy as np
+    lib = load()
+    sz = _i64(sizes)
+    n = ctypes.c_int64()
+    _check(lib.fft_describe_many_launches(sz, len(sizes), int(dtype), _sched(schedule), None, 0,
+                                        ctypes.byref(n)), "fft_describe_many_launches")
+    q = np.zeros(n.value + 1, dtype=np.int32)
+    _check(lib.fft_describe_many_launches(sz, len(sizes), int(dtype), _sched(schedule),
+                                        q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n.value + 1,
+                                        ctypes.byref(n)), "fft_describe_many_launches")
+    return q

@@ -680,7 +680,7 @@ constexpr int64_t kManyWaitDefaultUs = 2000000;  // 2 s per dependency wait
 namespace mfft {
 
 size_t many_workspace_bytes(const ManyPlan& mp) {
-  return (size_t)(kManyWsHeader + mp.count) * sizeof(int32_t);
+  return (size_t)(kManyWsHeader + mp.count + kManyMaxQueues) * sizeof(int32_t);
 }
 
 hipError_t many_reset_workspace(const ManyPlan& mp, void* ws) {
@@ -707,13 +707,14 @@ int many_alloc_workspace(const ManyPlan& mp, void** ws, size_t* bytes) {
   return FFT_OK;
 }
 
-hipError_t many_launch(const ManyPlan& mp, const void* in, void* out, void* ws, float scale,
-                       bool use_scale, bool inverse, hipStream_t s) {
+hipError_t many_launch(const ManyPlan& mp, const void* in, void* out, void* ws, int32_t* watchdog,
+                       float scale, bool use_scale, bool inverse, hipStream_t s) {
   if (!ws) return hipErrorInvalidValue;
   ManyArgs a = mp.args;
   a.in = in;
   a.out = out;
   a.ws = (int32_t*)ws;
+  a.watchdog = watchdog ? watchdog : (int32_t*)ws + 2;
   a.scale = scale;
   a.use_scale = use_scale ? 1 : 0;
   a.inverse = inverse ? 1 : 0;
@@ -722,6 +723,10 @@ hipError_t many_launch(const ManyPlan& mp, const void* in, void* out, void* ws, 
 
 void many_free(ManyPlan& mp) {
   if (mp.d_items) hipFree(mp.d_items);
+  if (mp.d_itx) hipFree(mp.d_itx);
+  if (mp.d_q_off) hipFree(mp.d_q_off);
+  mp.d_itx = nullptr;
+  mp.d_q_off = nullptr;
   if (mp.d_xf) hipFree(mp.d_xf);
   if (mp.d_order) hipFree(mp.d_order);
   if (mp.d_order_off) hipFree(mp.d_order_off);
@@ -747,6 +752,11 @@ struct ManyOptions {
   // split transform i + k, so its intermediate is still in the last-level
   // cache when it is read back
   int lag = 0;
+  // per length 2^L: two passes forced (2) or refused (1), 0 = by `pass2`;
+  // and log2 of the first-pass length N1 of a two-pass transform (0 = the
+  // default, ceil(L/2) capped at the longest tile)
+  int passes_for[FFT_MAX_LOG2_1D + 1] = {};
+  int lg1_for[FFT_MAX_LOG2_1D + 1] = {};
 };
 
 int parse_many_schedule(const char* s, ManyOptions* o) {
@@ -771,14 +781,33 @@ int parse_many_schedule(const char* s, ManyOptions* o) {
     char* e = nullptr;
     long v = strtol(val.c_str(), &e, 10);
     if (!e || *e) return FFT_ERR_INVALID_ARGUMENT;
+    // per-length items: 'n1.L=l1' and 'pass.L=1|2'
+    const size_t dot = key.find('.');
+    if (dot != std::string::npos) {
+      const std::string k0 = key.substr(0, dot), k1 = key.substr(dot + 1);
+      char* e2 = nullptr;
+      const long L = strtol(k1.c_str(), &e2, 10);
+      if (k1.empty() || !e2 || *e2 || L < 1 || L > FFT_MAX_LOG2_1D) return FFT_ERR_INVALID_ARGUMENT;
+      if (k0 == "n1") {
+        if (v < 1 || v >= L) return FFT_ERR_INVALID_ARGUMENT;
+        o->lg1_for[L] = (int)v;
+      } else if (k0 == "pass") {
+        if (v != 1 && v != 2) return FFT_ERR_INVALID_ARGUMENT;
+        o->passes_for[L] = (int)v;
+      } else {
+        return FFT_ERR_INVALID_ARGUMENT;
+      }
+      continue;
+    }
     if (key == "p") o->P = (int)v;
     else if (key == "threads") o->threads = (int)v;
     else if (key == "pass2") {
       if (v < 1) return FFT_ERR_INVALID_ARGUMENT;
       o->pass2 = (int)v;
     } else if (key == "pipe") {
-      if (v != 0 && v != 1) return FFT_ERR_INVALID_ARGUMENT;
+      if (v < 0 || v > 2) return FFT_ERR_INVALID_ARGUMENT;
       o->pipe = (int)v;
+
     } else if (key == "lag") {
       if (v < 0 || v > (1 << 24)) return FFT_ERR_INVALID_ARGUMENT;
       o->lag = (int)v;
@@ -1033,7 +1062,11 @@ int exec_impl(fft_plan_t p, const void* in, void* out, void* stream, void* ws_ov
     }
     hipEvent_t* slot = prof_slot(p, s);
     if (slot) hipEventRecord(slot[0], s);
-    hipError_t e = many_launch(p->many, in, out, plan_ws, (float)p->scale, p->scale_user, p->direction > 0, s);
+    // with the static scratch, bounded waits flag the plan's own watchdog word
+    // (read by fft_many_watchdog) when the plan has a workspace
+    int32_t* wd = (ws_over && p->ws) ? (int32_t*)p->ws + 2 : nullptr;
+    hipError_t e = many_launch(p->many, in, out, plan_ws, wd, (float)p->scale, p->scale_user,
+                               p->direction > 0, s);
     if (slot) hipEventRecord(slot[1], s);
     if (e != hipSuccess) return hip_fail(e);
     prof_commit(p, s);
@@ -1378,7 +1411,27 @@ struct ManyBuild {
   int64_t points = 0, pass_points = 0;
   double flops = 0;
   bool has_split = false;
+  // two-launch kernel: items (in `items`) in launch order, launch p running
+  // items q_off[p] .. q_off[p+1]-1
+  std::vector<int32_t> q_off;
 };
+
+// The two launches of the two-launch kernel (pipe 2): every first-pass tile,
+// then the one-pass tiles, in the first; every second-pass tile in the
+// second (the kernel boundary orders each transform's passes).  Within a
+// launch, items keep the queue's order (largest transforms first).
+// Reorders mb->items in place.
+void split_launches(ManyBuild* mb) {
+  std::vector<ManyItem> a, one, b;
+  for (const ManyItem& it : mb->items)
+    (it.kind == MANY_A ? a : it.kind == MANY_B ? b : one).push_back(it);
+  mb->items.clear();
+  mb->items.insert(mb->items.end(), a.begin(), a.end());
+  mb->items.insert(mb->items.end(), one.begin(), one.end());
+  mb->q_off = {0, (int32_t)mb->items.size(), 0};
+  mb->items.insert(mb->items.end(), b.begin(), b.end());
+  mb->q_off[2] = (int32_t)mb->items.size();
+}
 
 // Host-only part of a batched plan: per-transform descriptors, the ordered
 // work queue and the one-pass groups.  No GPU calls.
@@ -1415,10 +1468,19 @@ int build_many(const int64_t* sizes, int64_t count, int dtype, int direction, co
     x.off = off;
     x.lg = lg;
     // two passes need two sub-lengths of at least 2 points each
-    const bool split = (lg >= opt.pass2 || lg > max_tile) && lg >= 2;
+    bool split = (lg >= opt.pass2 || lg > max_tile) && lg >= 2;
+    if (opt.passes_for[lg] == 2 || opt.lg1_for[lg]) {
+      if (lg < 2) return FFT_ERR_INVALID_ARGUMENT;
+      split = true;
+    }
+    if (opt.passes_for[lg] == 1) {
+      if (lg > max_tile) return FFT_ERR_INVALID_ARGUMENT;
+      split = false;
+    }
     if (split) {
-      x.lg1 = (lg + 1) / 2;
-      if (x.lg1 > max_tile) x.lg1 = max_tile;
+      x.lg1 = opt.lg1_for[lg] ? opt.lg1_for[lg] : (lg + 1) / 2;
+      if (!opt.lg1_for[lg] && x.lg1 > max_tile) x.lg1 = max_tile;
+      if (x.lg1 > max_tile || lg - x.lg1 > max_tile || x.lg1 < 1 || lg - x.lg1 < 1) return FFT_ERR_INVALID_ARGUMENT;
       const int64_t N2 = (int64_t)1 << (lg - x.lg1);
       const int wa = tile_lines(x.lg1, opt.P, opt.threads);
       x.nA = (int32_t)((N2 + wa - 1) / wa);
@@ -1489,7 +1551,8 @@ int build_many(const int64_t* sizes, int64_t count, int dtype, int direction, co
     }
   }
   while (b_next < split_ids.size()) push_b(split_ids[b_next++]);
-  if (items.size() > (size_t)INT32_MAX) return FFT_ERR_UNSUPPORTED_SIZE;
+  if (items.size() > (size_t)INT32_MAX / 2) return FFT_ERR_UNSUPPORTED_SIZE;
+  if (opt.pipe == 2) split_launches(mb);
   return FFT_OK;
 }
 
@@ -1520,6 +1583,29 @@ int fft_describe_many(const int64_t* sizes, int64_t count, int dtype, const char
   for (int64_t i = 0; i < count; ++i) {
     if (first_len) first_len[i] = mb.xf[i].nA ? (1 << mb.xf[i].lg1) : 0;
     if (first_tiles) first_tiles[i] = mb.xf[i].nA;
+  }
+  return FFT_OK;
+}
+
+int fft_describe_many_launches(const int64_t* sizes, int64_t count, int dtype, const char* schedule,
+                               int32_t* q_off, int64_t max_q, int64_t* n_q) {
+  if (!n_q) return FFT_ERR_INVALID_ARGUMENT;
+  ManyBuild mb;
+  int rc = build_many(sizes, count, dtype, FFT_FORWARD, schedule, &mb);
+  if (rc) return rc;
+  if (mb.q_off.empty()) {
+    *n_q = 1;
+    if (q_off) {
+      if (max_q < 2) return FFT_ERR_INVALID_ARGUMENT;
+      q_off[0] = 0;
+      q_off[1] = (int32_t)mb.items.size();
+    }
+    return FFT_OK;
+  }
+  *n_q = (int64_t)mb.q_off.size() - 1;
+  if (q_off) {
+    if (max_q < (int64_t)mb.q_off.size()) return FFT_ERR_INVALID_ARGUMENT;
+    for (size_t i = 0; i < mb.q_off.size(); ++i) q_off[i] = mb.q_off[i];
   }
   return FFT_OK;
 }
@@ -1604,6 +1690,29 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
     return FFT_OK;
   };
   rc = upload((void**)&mp.d_items, items.data(), items.size() * sizeof(ManyItem));
+  if (!rc && opt.pipe == 2) {
+    // one self-contained record per item, grouped by queue
+    std::vector<ManyItemX> itx(items.size());
+    for (size_t i = 0; i < items.size(); ++i) {
+      const ManyItem& it = items[i];
+      ManyItemX& d = itx[i];
+      memset(&d, 0, sizeof(d));
+      d.kind = it.kind;
+      d.lg = it.lg;
+      d.a = it.a;
+      d.b = it.b;
+      if (it.kind != MANY_SINGLE) {
+        const ManyXform& x = xf[it.a];
+        d.off = x.off;
+        d.tw_lo = x.tw_lo;
+        d.tw_step = x.tw_step;
+        d.lg1 = x.lg1;
+        d.lgN = x.lg;
+      }
+    }
+    rc = upload((void**)&mp.d_itx, itx.data(), itx.size() * sizeof(ManyItemX));
+    if (!rc) rc = upload((void**)&mp.d_q_off, mb.q_off.data(), mb.q_off.size() * sizeof(int32_t));
+  }
   if (!rc) rc = upload((void**)&mp.d_xf, xf.data(), xf.size() * sizeof(ManyXform));
   if (!rc) rc = upload((void**)&mp.d_order, order.data(), order.size() * sizeof(int32_t));
   std::vector<int64_t> order_off(order.size());
@@ -1664,6 +1773,10 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
   a.n_items = (int32_t)items.size();
   a.n_xforms = (int32_t)count;
   a.wait_ticks = kManyWaitDefaultUs * 100;
+  a.itx = mp.d_itx;
+  a.q_off = mp.d_q_off;
+  a.phase = 0;
+  a.n_phase2 = opt.pipe == 2 ? mb.q_off[2] - mb.q_off[1] : 0;
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
   if (e != hipSuccess) {
@@ -1672,6 +1785,9 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
   }
   const int per_cu = std::max(1, var->max_blocks_per_cu());
   mp.grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * cus, mp.n_items));
+  // the two-launch kernel runs the full resident grid: with claims from the
+  // queue head every workgroup is useful until the launch's items run out
+  if (opt.pipe == 2) mp.grid = std::max(1, per_cu * cus);
   rc = many_alloc_workspace(mp, &p->ws, &p->ws_bytes);
   if (rc) {
     fft_destroy(p);

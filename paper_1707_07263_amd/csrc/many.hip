@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(NT) k_many(ManyArgs a) {
   const int tid = threadIdx.x;
   int* queue = a.ws;
   int* exits = a.ws + 1;
-  int* watchdog = a.ws + 2;
+  int* watchdog = a.watchdog;
   int* done = a.ws + kManyWsHeader;
   for (;;) {
     if (tid == 0) s_item = atomicAdd(queue, 1);
@@ -436,7 +436,7 @@ __global__ void __launch_bounds__(NT, 1) k_many_pipe(ManyArgs a) {
   float2* rowl = lds + XN + TWN;
   const int tid = threadIdx.x;
   int* exits = a.ws + 1;
-  int* watchdog = a.ws + 2;
+  int* watchdog = a.watchdog;
   int* done = a.ws + kManyWsHeader;
 
   // Thread 0: bounded wait for transform x's first pass (same protocol as
@@ -631,6 +631,378 @@ __global__ void __launch_bounds__(NT, 1) k_many_pipe(ManyArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two-launch pipelined kernel.  The passes of the split transforms are
+// synchronised the way the paper synchronises its passes: by a kernel
+// boundary (Sec. 2.3.3).  An exec queues two launches of the same persistent
+// kernel: the first runs every first-pass tile and every one-pass tile, the
+// second every second-pass tile.  Inside a launch no workgroup ever waits for
+// another, so there are no counters, no device-wide fences and no bounded
+// waits; items are claimed from the launch's atomic queue head, two ahead,
+// so only running workgroups hold items and the tiles spread evenly however
+// many workgroups are resident.  (Completion counters inside one launch need
+// a device-scope release per first-pass tile, and each costs an L2
+// write-back and a full memory wait on that CU: measured at about 10 us per
+// release in a streaming kernel of this shape, which is what held the
+// single-launch kernel above to a third of peak.)
+// ---------------------------------------------------------------------------
+
+// Wait until at most N vector-memory operations of this wave are in flight.
+template <int N>
+__device__ __forceinline__ void vm_wait() {
+  // s_waitcnt: vmcnt in bits [3:0] and [15:14], expcnt [6:4] = 7 and
+  // lgkmcnt [11:8] = 15 left at their maxima (not waited for)
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// The per-lane loads of an item, issued ahead of its butterflies.
+template <int P>
+struct XPre {
+  float2 v[P];
+  float2 rown[2];
+  float2 lon, hin;
+};
+
+// Issue the loads of item d (lg >= 1): data and, for a first pass, the
+// inter-pass twiddle inputs.  `base` is the lane's line offset for one-pass
+// items (loaded earlier).
+template <int P, int NT, typename TS>
+__device__ __forceinline__ void xprefetch(const ManyArgs& a, const ManyItemX& d, int64_t base, XPre<P>& pre,
+                                          int tid) {
+  const int lg = d.lg;
+  const int lpp = lg < ilog2(P) ? lg : ilog2(P);
+  const int lt = lg - lpp;            // log2 T
+  const int lw = ilog2(NT) - lt;      // log2 W
+  const int PP = 1 << lpp;
+  const bool mfast = d.kind != MANY_SINGLE;
+  const int m = mfast ? (tid & ((1 << lw) - 1)) : (tid >> lt);
+  const int t = mfast ? (tid >> lw) : (tid & ((1 << lt) - 1));
+  const TS* src = reinterpret_cast<const TS*>(d.kind == MANY_B ? a.out : a.in);
+  // Every lane issues every load: lanes past the last line of a partial tile
+  // read a valid line (the first of a one-pass tile, the last of a strip)
+  // and are not stored.
+  int64_t ibase, ielem = 1;
+  if (d.kind == MANY_SINGLE) {
+    ibase = base;
+  } else {
+    const int64_t n1 = (int64_t)1 << d.lg1, n2 = (int64_t)1 << (d.lgN - d.lg1);
+    const int64_t nl = d.kind == MANY_A ? n2 : n1;
+    const int64_t line = min(((int64_t)d.b << lw) + m, nl - 1);
+    ibase = d.off + line;
+    ielem = nl;
+    if (d.kind == MANY_A && many_step_rows<P, NT>(lg)) {
+      const int64_t line0 = (int64_t)d.b << lw;
+      const int wpp = 1 << (lw + lpp);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int i = tid + k * NT;
+        if (i < wpp) {
+          const int64_t ln = line0 + (i >> lpp) < n2 ? line0 + (i >> lpp) : n2 - 1;
+          pre.rown[k] = a.tw[d.tw_step + (ln << lpp) + (i & (PP - 1))];
+        }
+      }
+      // the store mapping is point-fastest: line tid / T, point tid % T
+      const int64_t lst = line0 + (tid >> lt);
+      const uint32_t jb = (uint32_t)(lst < n2 ? lst : n2 - 1) * (uint32_t)(tid & ((1 << lt) - 1));
+      pre.lon = a.tw[d.tw_lo + (jb & (uint32_t)(n1 - 1))];
+      pre.hin = a.tw[d.tw_lo + n1 + (jb >> d.lg1)];
+    }
+  }
+  const int64_t step = ielem << lt;
+  const TS* p0 = src + ibase + (int64_t)t * ielem;
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+    if (q < PP) pre.v[q] = load_c(p0 + q * step);
+}
+
+// Butterflies and epilogue of one item (its points in v, outputs left in v
+// in the store mapping, times the inter-pass twiddle and the scale,
+// conjugated back for the inverse).
+template <int L, int P, int NT>
+__device__ __forceinline__ void xcompute(const ManyArgs& a, const ManyItemX& d, float2* v, float2* xch,
+                                         const float2* twl, const float2* rowl, float2 tw_base, int tid) {
+  using S = Sched<L, P>;
+  constexpr int T = S::T;
+  constexpr int PP = S::PP;
+  constexpr int W = NT / T;
+  constexpr bool kRows = many_step_rows<P, NT>(ilog2(L));
+  static_assert(W >= 1 && W * T == NT, "tile must fill the workgroup");
+  const bool mfast_in = d.kind != MANY_SINGLE;
+  const bool mfast_out = d.kind == MANY_B;
+  int m = mfast_in ? tid % W : tid / T;
+  int t = mfast_in ? tid / W : tid % T;
+  const int m_st = mfast_out ? tid % W : tid / T;
+  const int t_st = mfast_out ? tid / W : tid % T;
+  const bool first = d.kind != MANY_B;
+  const bool last = d.kind != MANY_A;
+  const uint32_t sgn_in = (first && a.inverse) ? 0x80000000u : 0u;
+#pragma unroll
+  for (int q = 0; q < PP; ++q) v[q].y = __uint_as_float(__float_as_uint(v[q].y) ^ sgn_in);
+
+  run_stages<L, P, W, 0, 1>(v, xch, m, t, m_st, t_st, mfast_in != mfast_out, twl);
+
+  float scale;
+  if (d.kind == MANY_SINGLE)
+    scale = a.use_scale ? a.scale : (a.inverse ? 1.f / (float)L : 1.f);
+  else if (d.kind == MANY_A)
+    scale = (a.inverse && !a.use_scale) ? 1.f / (float)(1 << d.lg1) : 1.f;
+  else
+    scale = a.use_scale ? a.scale : (a.inverse ? 1.f / (float)(1 << (d.lgN - d.lg1)) : 1.f);
+  const uint32_t sgn_out = (last && a.inverse) ? 0x80000000u : 0u;
+  const uint32_t line_st = (uint32_t)(d.b * W + m);
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    float2 y = v[q];
+    if (d.kind == MANY_A) {
+      if constexpr (kRows) {
+        y = cmul(y, cmul(tw_base, rowl[m * PP + q]));
+      } else {
+        const uint32_t jj = line_st * (uint32_t)(t + q * T);
+        const float2* lo = a.tw + d.tw_lo;
+        const float2* hi = lo + ((int64_t)1 << d.lg1);
+        y = cmul(y, cmul(hi[jj >> d.lg1], lo[jj & ((1u << d.lg1) - 1u)]));
+      }
+    }
+    y = cscale(y, scale);
+    y.y = __uint_as_float(__float_as_uint(y.y) ^ sgn_out);
+    v[q] = y;
+  }
+}
+
+// Stores of an item whose outputs xcompute left in v.  `base` is the lane's
+// line offset for one-pass items.
+template <int L, int P, int NT, typename TS>
+__device__ __forceinline__ void xstore(const ManyArgs& a, const ManyItemX& d, const float2* v, int64_t base,
+                                       int tid) {
+  using S = Sched<L, P>;
+  constexpr int T = S::T;
+  constexpr int PP = S::PP;
+  constexpr int W = NT / T;
+  const bool mfast_out = d.kind == MANY_B;
+  const int m = mfast_out ? tid % W : tid / T;
+  const int t = mfast_out ? tid / W : tid % T;
+  TS* dst = reinterpret_cast<TS*>(a.out);
+  int64_t obase, oelem = 1;
+  bool ok;
+  if (d.kind == MANY_SINGLE) {
+    ok = m < d.b;
+    obase = base;
+  } else {
+    const int64_t N1 = (int64_t)1 << d.lg1, N2 = (int64_t)1 << (d.lgN - d.lg1);
+    const int64_t line = (int64_t)d.b * W + m;
+    if (d.kind == MANY_A) {
+      ok = line < N2;
+      obase = d.off + line * N1;  // T[n2*N1 + k1]
+    } else {
+      ok = line < N1;
+      obase = d.off + line;  // X[k1 + N1*k2]
+      oelem = N1;
+    }
+  }
+  if (ok) {
+#pragma unroll
+    for (int q = 0; q < PP; ++q) store_c(dst + obase + (int64_t)(t + q * T) * oelem, v[q]);
+  }
+}
+
+// Descriptor of queue slot i, read with scalar loads (i is uniform).
+__device__ __forceinline__ ManyItemX xitem(const ManyArgs& a, int i, int hi) {
+  ManyItemX d{};
+  d.kind = -1;
+  d.lg = 0;
+  if (i < hi) {
+    // constant address space: uniform loads from it are scalar loads
+    typedef const int32_t __attribute__((address_space(4)))* cptr;
+    const cptr p = (cptr)(a.itx + __builtin_amdgcn_readfirstlane(i));
+    int32_t w[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) w[k] = p[k];
+    __builtin_memcpy(&d, w, sizeof(d));
+  }
+  return d;
+}
+
+// Line offset of this lane's line in a one-pass item (lines past the tile's
+// last read its first line).
+template <int P>
+__device__ __forceinline__ int64_t xbase(const ManyArgs& a, const ManyItemX& d, int tid) {
+  const int lt = d.lg - (d.lg < ilog2(P) ? d.lg : ilog2(P));
+  const int m = tid >> lt;
+  return a.order_off[d.a + (m < d.b ? m : 0)];
+}
+
+#define MANY_XCD_SWITCH(LG, CALL)                          \
+  switch (LG) {                                            \
+    case 1: { constexpr int L = 2; CALL; } break;          \
+    case 2: { constexpr int L = 4; CALL; } break;          \
+    case 3: { constexpr int L = 8; CALL; } break;          \
+    case 4: { constexpr int L = 16; CALL; } break;         \
+    case 5: { constexpr int L = 32; CALL; } break;         \
+    case 6: { constexpr int L = 64; CALL; } break;         \
+    case 7: { constexpr int L = 128; CALL; } break;        \
+    case 8: { constexpr int L = 256; CALL; } break;        \
+    case 9: { constexpr int L = 512; CALL; } break;        \
+    case 10: { constexpr int L = 1024; CALL; } break;      \
+    case 11: { constexpr int L = 2048; CALL; } break;      \
+    case 12: { constexpr int L = 4096; CALL; } break;      \
+    default: break;                                        \
+  }
+
+// One loop iteration handles three items: it stores the results of the
+// previous item p (left in registers), transforms the current item c (whose
+// points were loaded during p) and issues the loads of the next item n.  So
+// every vector-memory operation is issued about one item before anything
+// waits for it, and the one full wait at the top of each iteration (for c's
+// points) costs nothing even though it also covers p's stores, issued an
+// iteration earlier: the pipelining does not depend on the compiler
+// computing exact wait counts across the many item paths.
+// Launch `a.phase` runs the items q_off[phase] .. q_off[phase+1]-1.
+template <typename TS, int P, int NT, int MAXLG>
+__global__ void __launch_bounds__(NT, 1) k_many_2l(ManyArgs a) {
+  static_assert(NT * P >= (1 << MAXLG) && MAXLG <= 12, "tile lengths 2 .. 2^12");
+  constexpr int XN = many_lds_max<P, NT, MAXLG>();
+  constexpr int TWN = many_tw_total<P, MAXLG>();
+  __shared__ float2 lds[XN + TWN + 2 * NT];
+  __shared__ int s_idx[2], s_first[2], s_last;
+  float2* xch = lds;
+  float2* twl = lds + XN;
+  float2* rowl = lds + XN + TWN;
+  const int tid = threadIdx.x;
+  int* heads = a.ws + kManyWsHeader + a.n_xforms;  // [phase]: queue head; [8 + phase]: exits
+  const int ph = a.phase;
+  const int lo = a.q_off[ph], hi = a.q_off[ph + 1];
+  int* head = heads + ph;
+  int* exits = heads + 8 + ph;
+  constexpr int kNoClaim = 1 << 30;
+
+  // stage twiddles: one contiguous copy of the plan's LDS image
+  {
+    constexpr int K = (TWN + NT - 1) / NT;
+    float2 tmp[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (tid + k * NT < a.tw_img_len) tmp[k] = a.tw_img[tid + k * NT];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (tid + k * NT < a.tw_img_len) twl[tid + k * NT] = tmp[k];
+  }
+
+  // first two claims
+  if (tid == 0) {
+    s_first[0] = lo + atomicAdd(head, 1);
+    s_first[1] = lo + atomicAdd(head, 1);
+  }
+  __syncthreads();  // stage twiddles and claims visible
+  int c = min(s_first[0], hi);
+  int n = min(s_first[1], hi);
+  ManyItemX dc = xitem(a, c, hi);
+  ManyItemX dn = xitem(a, n, hi);
+  XPre<P> pre;
+  int64_t base_c = 0, base_n = 0;
+  if (c < hi) {
+    if (dc.kind == MANY_SINGLE) base_c = xbase<P>(a, dc, tid);
+    if (dc.lg >= 1) xprefetch<P, NT, TS>(a, dc, base_c, pre, tid);
+  }
+  if (n < hi && dn.kind == MANY_SINGLE) base_n = xbase<P>(a, dn, tid);
+  int claim = kNoClaim;  // thread 0: raw value of the claim in flight
+  if (tid == 0) claim = atomicAdd(head, 1);
+
+  float2 v[P];
+  ManyItemX dp{};
+  dp.kind = -1;
+  dp.lg = 0;
+  int64_t base_p = 0;
+  int par = 0;
+
+  while (c < hi) {
+    // ---- top: every memory operation issued by the previous iteration done
+    vm_wait<0>();
+    // stores of the previous item
+    if (dp.kind >= 0) {
+      MANY_XCD_SWITCH(dp.lg, (xstore<L, P, NT, TS>(a, dp, v, base_p, tid)));
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) v[k] = pre.v[k];
+    float2 tw_base = make_float2(1.f, 0.f);
+    if (dc.kind == MANY_A && dc.lg >= 1 && many_step_rows<P, NT>(dc.lg)) {
+      const int lpp = dc.lg < ilog2(P) ? dc.lg : ilog2(P);
+      const int wpp = (NT << (2 * lpp)) >> dc.lg;  // W * PP <= 2 * NT
+      rowl[tid] = pre.rown[0];
+      if (tid + NT < wpp) rowl[tid + NT] = pre.rown[1];
+      tw_base = cmul(pre.hin, pre.lon);
+    }
+    // the index of the item after n
+    if (tid == 0) s_idx[par] = min(lo + claim, hi);
+    lds_barrier();  // also: step rows visible
+    const int n2 = s_idx[par];
+    par ^= 1;
+    claim = kNoClaim;
+    if (n2 < hi && tid == 0) claim = atomicAdd(head, 1);
+    if (n < hi && dn.lg >= 1) xprefetch<P, NT, TS>(a, dn, base_n, pre, tid);
+    const ManyItemX dn2 = xitem(a, n2, hi);
+
+    // ---- the current item
+    if (dc.lg == 0) {
+      many_tile1<NT, TS>(a, ManyItem{dc.kind, dc.lg, dc.a, dc.b}, tid);
+    } else {
+      MANY_XCD_SWITCH(dc.lg, (xcompute<L, P, NT>(a, dc, v, xch, twl + ManyTwOff<P, (ilog2(L) > 0 ? ilog2(L) : 1)>::value, rowl, tw_base, tid)));
+    }
+    // line offsets of item n2 (one-pass items)
+    int64_t base_n2 = 0;
+    if (n2 < hi && dn2.kind == MANY_SINGLE) base_n2 = xbase<P>(a, dn2, tid);
+    lds_barrier();  // LDS reads of this item done before the next one writes
+
+    dp = dc;
+    base_p = base_c;
+    if (dc.lg == 0) dp.kind = -1;  // stored already
+    c = n;
+    dc = dn;
+    base_c = base_n;
+    n = n2;
+    dn = dn2;
+    base_n = base_n2;
+  }
+  // the last item's stores
+  if (dp.kind >= 0) {
+    MANY_XCD_SWITCH(dp.lg, (xstore<L, P, NT, TS>(a, dp, v, base_p, tid)));
+  }
+  // The last workgroup out resets this launch's queue head for the next exec.
+  __syncthreads();
+  if (tid == 0) {
+    const int fin = __hip_atomic_fetch_add(exits, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = fin == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_last && tid == 0) {
+    __hip_atomic_store(head, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(exits, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Both launches of an exec: first passes and one-pass tiles, then second
+// passes (the second launch is skipped when no transform is split).
+template <typename TS, int P, int NT, int MAXLG>
+hipError_t launch_many_2l(const ManyArgs& a, int grid, hipStream_t s) {
+  for (int ph = 0; ph < 2; ++ph) {
+    ManyArgs b = a;
+    b.phase = ph;
+    if (ph == 1 && a.n_phase2 == 0) break;
+    hipLaunchKernelGGL((k_many_2l<TS, P, NT, MAXLG>), dim3(grid), dim3(NT), 0, s, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename TS, int P, int NT, int MAXLG>
+int blocks_many_2l() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_many_2l<TS, P, NT, MAXLG>, NT, 0) != hipSuccess)
+    return 0;
+  return n;
+}
+
 template <typename TS, int P, int NT, int MAXLG>
 hipError_t launch_many_pipe(const ManyArgs& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL((k_many_pipe<TS, P, NT, MAXLG>), dim3(grid), dim3(NT), 0, s, a);
@@ -664,6 +1036,9 @@ int blocks_many() {
 // half the LDS; its registers still keep it to one workgroup per CU)
 #define MANY_PIPE(TS, DT, P, NT, MAXLG) \
   {DT, P, NT, 1, MAXLG, &launch_many_pipe<TS, P, NT, MAXLG>, &blocks_many_pipe<TS, P, NT, MAXLG>}
+// two launches (kernel boundary between the passes): 512 lanes, tiles up to 2^12
+#define MANY_2L(TS, DT, P, NT, MAXLG) \
+  {DT, P, NT, 2, MAXLG, &launch_many_2l<TS, P, NT, MAXLG>, &blocks_many_2l<TS, P, NT, MAXLG>}
 
 static const ManyVariant kManyVariants[] = {
     MANY_VARIANT(float2, DT_C64, 16, 256),   MANY_VARIANT(float2, DT_C64, 8, 256),
@@ -673,6 +1048,8 @@ static const ManyVariant kManyVariants[] = {
     MANY_PIPE(__half2, DT_C16F, 16, 512, 12),    MANY_PIPE(c16bf, DT_C16BF, 16, 512, 12),
     MANY_PIPE(float2, DT_C64, 16, 256, 11),      MANY_PIPE(__half2, DT_C16F, 16, 256, 11),
     MANY_PIPE(c16bf, DT_C16BF, 16, 256, 11),
+    MANY_2L(float2, DT_C64, 16, 512, 12),        MANY_2L(__half2, DT_C16F, 16, 512, 12),
+    MANY_2L(c16bf, DT_C16BF, 16, 512, 12),
 };
 
 int many_variant_count() { return (int)(sizeof(kManyVariants) / sizeof(kManyVariants[0])); }

@@ -39,6 +39,22 @@ struct ManyXform {
 
 constexpr int kManyMaxLg = 12;  // longest single-tile length: 2^12 points
 
+// Work item of the two-launch kernel: everything its loads, butterflies and
+// stores need, so that one scalar load per item fetches it.
+struct ManyItemX {
+  int32_t kind, lg;  // MANY_*; log2 of the tile's line length
+  int32_t a;         // transform (first/second pass) or first order slot (one pass)
+  int32_t b;         // tile (first/second pass) or lines in the tile (one pass)
+  int64_t off;       // element offset of the transform (first/second pass)
+  int64_t tw_lo;     // first pass: W_N^j tables (lo at tw_lo, hi at tw_lo + N1)
+  int64_t tw_step;   // first pass: step rows W_N^{n2*q*(N1/P)}
+  int32_t lg1, lgN;  // log2 N1 and log2 N (first/second pass)
+  int32_t pad[4];
+};
+static_assert(sizeof(ManyItemX) == 64, "one 64-byte record per item");
+
+constexpr int kManyMaxQueues = 16;  // ints after the counters: queue heads and exit counts
+
 struct ManyArgs {
   const void* in;
   void* out;
@@ -49,7 +65,7 @@ struct ManyArgs {
   const float2* tw;                   // base of the plan's tables
   int64_t stage_off[kManyMaxLg + 1];  // stage table of a 2^lg tile
   int32_t n_items, n_xforms;
-  int32_t* ws;                        // [0] queue head, [1] exits, [2] watchdog, [3..] done
+  int32_t* ws;                        // workspace (layout above kManyWsHeader)
   float scale;                        // used when use_scale != 0
   int32_t use_scale;                  // 0: per-transform default (1 or 1/N)
   int32_t inverse;
@@ -59,13 +75,24 @@ struct ManyArgs {
   // the kernel keeps them in LDS (copied there contiguously at launch)
   const float2* tw_img;
   int32_t tw_img_len;
+  // two-launch kernel: items in launch order, launch p running items
+  // q_off[p] .. q_off[p+1]-1 (p = phase: 0 first passes and one-pass tiles,
+  // 1 second passes); n_phase2 = q_off[2] - q_off[1]
+  const ManyItemX* itx;
+  const int32_t* q_off;
+  int32_t phase, n_phase2;
+  int32_t* watchdog;  // flag set when a bounded wait expires
 };
 
+// Workspace: [0] queue head (shared-queue kernel), [1] exits, [2] watchdog,
+// [3] unused, then one completion counter per transform, then
+// kManyMaxQueues ints for the two-launch kernel (queue head of launch p at
+// [p], its exit count at [8 + p]).
 constexpr int kManyWsHeader = 4;  // ints before the per-transform counters
 
 struct ManyVariant {
   int dtype, P, threads;
-  int pipe;    // 1: software-pipelined
+  int pipe;    // 1: software-pipelined; 2: software-pipelined, two launches per exec
   int max_lg;  // longest one-tile length, 2^max_lg
   hipError_t (*launch)(const ManyArgs&, int grid, hipStream_t);
   int (*max_blocks_per_cu)();
@@ -89,6 +116,8 @@ struct ManyPlan {
   bool active = false;
   const ManyVariant* var = nullptr;
   ManyItem* d_items = nullptr;
+  ManyItemX* d_itx = nullptr;
+  int32_t* d_q_off = nullptr;
   ManyXform* d_xf = nullptr;
   int32_t* d_order = nullptr;
   int64_t* d_order_off = nullptr;
@@ -107,8 +136,9 @@ struct ManyPlan {
 size_t many_workspace_bytes(const ManyPlan& mp);
 int many_alloc_workspace(const ManyPlan& mp, void** ws, size_t* bytes);
 hipError_t many_reset_workspace(const ManyPlan& mp, void* ws);
-hipError_t many_launch(const ManyPlan& mp, const void* in, void* out, void* ws, float scale,
-                       bool use_scale, bool inverse, hipStream_t s);
+// `watchdog`: the flag word bounded waits set (NULL: the one in `ws`).
+hipError_t many_launch(const ManyPlan& mp, const void* in, void* out, void* ws, int32_t* watchdog,
+                       float scale, bool use_scale, bool inverse, hipStream_t s);
 void many_free(ManyPlan& mp);
 
 }  // namespace mfft

@@ -77,7 +77,7 @@ def test_uneven_512_complex64(dev, which):
     assert np.all(per_transform_errors(inv, ref_inv, sizes) <= tol)
 
 
-@pytest.mark.parametrize("pipe", [None, "pipe=1;threads=512", "pipe=1;threads=256"])
+@pytest.mark.parametrize("pipe", [None, "pipe=1;threads=512", "pipe=1;threads=256", "pipe=2;threads=512"])
 @pytest.mark.parametrize("dt", ["f16", "bf16"])
 def test_uneven_512_16bit(dev, dt, pipe):
     code, tname = DT16[dt]
@@ -108,7 +108,10 @@ def test_uneven_512_16bit(dev, dt, pipe):
                                       "threads=512", "pass2=1", "lag=1", "lag=3;pass2=9",
                                       "pipe=1;threads=512", "pipe=1;threads=512;pass2=1",
                                       "pipe=1;threads=512;pass2=9;lag=2", "pipe=1;threads=256",
-                                      "pipe=1;threads=256;pass2=3"])
+                                      "pipe=1;threads=256;pass2=3", "pipe=2;threads=512",
+                                      "pipe=2;threads=512;pass2=1", "pipe=2;threads=512;pass2=9",
+                                      "pipe=2;threads=512;pass.11=2;pass.12=2;n1.16=6;n1.15=9;n1.14=7",
+                                      "threads=512;n1.16=10;pass.9=2;n1.5=2"])
 def test_many_schedules_and_small_sizes(dev, schedule):
     # every length 2^0..2^16 twice, shuffled, under each compiled schedule
     g = workloads.rng(77)
@@ -124,7 +127,7 @@ def test_many_schedules_and_small_sizes(dev, schedule):
 
 
 @pytest.mark.parametrize("schedule", ["lag=0", "lag=2", "threads=512;lag=1", "pipe=1;threads=512",
-                                      "pipe=1;threads=256"])
+                                      "pipe=1;threads=256", "pipe=2;threads=512"])
 def test_many_16x2p20_lagged_queue(dev, schedule):
     # sixteen 2^20-point transforms in one launch, second passes interleaved
     # with later first passes
@@ -159,7 +162,7 @@ def test_many_inverse_scale_and_repeat(dev):
         capi.fft_destroy(h)
 
 
-@pytest.mark.parametrize("schedule", [None, "pipe=1;threads=512", "pipe=1;threads=256"])
+@pytest.mark.parametrize("schedule", [None, "pipe=1;threads=512", "pipe=1;threads=256", "pipe=2;threads=512"])
 def test_many_graph_capture_replay(dev, schedule):
     sizes, packed = workloads.uneven_batch(128, 8, 16, seed=31)
     xt = to_gpu_c64(packed, dev)
@@ -250,3 +253,44 @@ def test_many_errors(dev):
         capi.fft_destroy(h)
     ref = oracle.fft_many(x.astype(np.complex64), sizes)
     assert per_transform_errors(xt.cpu().numpy(), ref, np.array(sizes)).max() <= 1e-5
+
+
+@pytest.mark.parametrize("schedule", ["pipe=2;threads=512", "pipe=2;threads=512;pass2=9"])
+def test_many_two_launch_repeat_inverse_inplace(dev, schedule):
+    # two launches per exec: repeated execs of one plan agree bitwise (each
+    # launch resets its own queue head), the inverse with the default and a
+    # caller scale matches the oracle, and a batch of one-pass lengths runs
+    # in place (one launch)
+    sizes, packed = workloads.uneven_batch(200, 4, 16, seed=23)
+    xc = packed.astype(np.complex64)
+    xt = to_gpu_c64(xc, dev)
+    h = capi.fft_plan_many_ex(list(sizes), capi.FFT_C64, capi.FFT_FORWARD, schedule)
+    try:
+        outs = []
+        for _ in range(3):
+            o = torch.empty_like(xt)
+            capi.fft_exec(h, xt.data_ptr(), o.data_ptr(), torch.cuda.current_stream().cuda_stream)
+            outs.append(o)
+        torch.cuda.synchronize()
+        for o in outs[1:]:
+            assert torch.equal(o, outs[0])
+        got = outs[0].cpu().numpy()
+    finally:
+        capi.fft_destroy(h)
+    tol = 1e-6 * np.maximum(1.0, np.log2(sizes.astype(np.float64)))
+    assert np.all(per_transform_errors(got, oracle.fft_many(xc, sizes), sizes) <= tol)
+    inv = run_many_c64(got, sizes, dev, inverse=True, schedule=schedule)
+    assert np.all(per_transform_errors(inv, oracle.fft_many(got, sizes, inverse=True), sizes) <= tol)
+    adj = run_many_c64(xc, sizes, dev, inverse=True, scale=1.0, schedule=schedule)
+    assert np.all(per_transform_errors(adj, oracle.fft_many(xc, sizes, inverse=True, scale=1.0), sizes) <= tol)
+    one = np.array([1 << e for e in (8, 6, 7, 3, 5, 1, 8, 4)], dtype=np.int64)  # one pass under both
+    x1 = workloads.normal_batch(int(one.sum()), 1, seed=5)[0].astype(np.complex64)
+    b = to_gpu_c64(x1, dev)
+    h = capi.fft_plan_many_ex(list(one), capi.FFT_C64, capi.FFT_FORWARD, schedule)
+    try:
+        capi.fft_exec(h, b.data_ptr(), b.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+    finally:
+        capi.fft_destroy(h)
+    tol1 = 1e-6 * np.maximum(1.0, np.log2(one.astype(np.float64)))
+    assert np.all(per_transform_errors(b.cpu().numpy(), oracle.fft_many(x1, one), one) <= tol1)

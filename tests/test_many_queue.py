@@ -211,3 +211,39 @@ def test_queue_pipelined_protocol(schedule):
     items, ft = check_queue([1 << 16] * 64, "pipe=1;threads=512")
     for workers in (1, 3, 256):
         simulate_ahead(items, ft, workers, np.random.default_rng(5 + workers))
+
+
+@pytest.mark.parametrize("schedule", ["pipe=2;threads=512", "pipe=2;threads=512;pass2=9",
+                                      "pipe=2;threads=512;pass.12=2;n1.16=6;n1.15=9"])
+def test_two_launch_split(schedule):
+    # the two-launch kernel: launch 0 holds every first-pass and one-pass
+    # tile, launch 1 every second-pass tile; every transform is covered
+    sizes = workloads.uneven_sizes(512, 8, 16, seed=3)
+    items, first_len, first_tiles = capi.fft_describe_many(list(sizes), capi.FFT_C64, schedule)
+    q = capi.fft_describe_many_launches(list(sizes), capi.FFT_C64, schedule)
+    assert len(q) == 3 and q[0] == 0 and q[2] == len(items)
+    l0, l1 = items[q[0]:q[1]], items[q[1]:q[2]]
+    assert np.all(l0[:, 0] != SECOND) and np.all(l1[:, 0] == SECOND)
+    check_queue(sizes, schedule)
+    split = {int(a) for a in np.nonzero(first_tiles)[0]}
+    assert {int(a) for a in l1[:, 2]} == split
+    # the per-length choices took effect
+    lg = np.log2(sizes).astype(int)
+    if "n1.16=6" in schedule:
+        assert np.all(first_len[lg == 16] == 64) and np.all(first_len[lg == 15] == 512)
+    if "pass.12=2" in schedule:
+        assert np.all(first_tiles[lg == 12] > 0)
+
+
+def test_per_length_schedule_items():
+    sizes = [1 << 14, 1 << 9, 1 << 16]
+    _, fl, ft = capi.fft_describe_many(sizes, capi.FFT_C64, "n1.14=5;pass.9=2;n1.16=12")
+    assert list(fl) == [32, 32, 4096] and all(ft > 0)
+    _, fl, ft = capi.fft_describe_many(sizes + [1 << 12], capi.FFT_C64, "pass.12=2;pass.9=1")
+    assert fl[3] == 64 and ft[3] > 0 and fl[1] == 0
+    _, fl, ft = capi.fft_describe_many(sizes + [1 << 12], capi.FFT_C64, "pass2=9;pass.12=1")
+    assert fl[3] == 0 and ft[3] == 0 and fl[1] > 0
+    for bad in ("n1.16=13", "n1.16=3", "pass.13=1", "pass.9=3", "n1.0=1", "n1.x=2", "nx.9=2"):
+        with pytest.raises(capi.FFTError):
+            capi.fft_describe_many(sizes + [1 << 15, 1 << 13], capi.FFT_C64, bad)
+    assert len(capi.fft_describe_many_launches(sizes, capi.FFT_C64, None)) == 2
