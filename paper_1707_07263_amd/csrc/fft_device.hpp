@@ -226,7 +226,22 @@ struct PassArgs {
   // permutation happens in place)
   const int32_t* line_map;
   int32_t tr_shift;
+  // row pass of the blocked 2-D plan: outputs go to column blocks of
+  // 2^blk_lg columns, block j of an image holding columns j*2^blk_lg ..
+  // (j+1)*2^blk_lg - 1 of its 2^blk_rows_lg rows, row after row (0: natural
+  // order)
+  int32_t blk_lg, blk_rows_lg;
 };
+
+// Where point t + q*T of row `line` goes in the blocked layout: the lane's
+// first element, and the step between its points (T a multiple of the block
+// width, so a lane stays in one column of a block as q runs).
+__device__ __forceinline__ int64_t blk_base(const PassArgs& a, int64_t line, int t) {
+  const int64_t img = line >> a.blk_rows_lg;
+  const int64_t r = line & ((1 << a.blk_rows_lg) - 1);
+  return img * (a.out_line << a.blk_rows_lg) + ((int64_t)(t >> a.blk_lg) << (a.blk_rows_lg + a.blk_lg)) +
+         (r << a.blk_lg) + (t & ((1 << a.blk_lg) - 1));
+}
 
 __device__ __forceinline__ int row_transpose(int r, int sh) {
   return ((r & ((1 << sh) - 1)) << sh) | (r >> sh);
@@ -471,7 +486,11 @@ k_strip(PassArgs a) {
     const bool ok = a.line_map ? true : line < a.lines;
     TS* dst = reinterpret_cast<TS*>(a.out) + bat * a.out_batch + (int64_t)line * a.out_line +
               (int64_t)t * a.out_elem;
-    const int64_t step = (int64_t)T * a.out_elem;
+    int64_t step = (int64_t)T * a.out_elem;
+    if (!TWID && STOREM == 0 && a.blk_lg) {
+      dst = reinterpret_cast<TS*>(a.out) + blk_base(a, line, t);
+      step = (int64_t)T << a.blk_rows_lg;
+    }
     // inter-pass twiddle W_N^{row*(t + q*T)} = W_N^{row*t} * W_N^{row*q*T}
     // (row = line >> tw_line_shift): one base per lane, and a step row
     // shared by the lanes of a line
@@ -624,7 +643,11 @@ k_pipe(PassArgs a) {
     const int line_st = lmap ? line : min(line, a.lines - 1);
     TS* dst = reinterpret_cast<TS*>(a.out) + bat * a.out_batch + (int64_t)line_st * a.out_line +
               (int64_t)t * a.out_elem;
-    const int64_t step = (int64_t)T * a.out_elem;
+    int64_t step = (int64_t)T * a.out_elem;
+    if (!TWID && STOREM == 0 && a.blk_lg) {
+      dst = reinterpret_cast<TS*>(a.out) + blk_base(a, line_st, t);
+      step = (int64_t)T << a.blk_rows_lg;
+    }
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
       float2 y = v[q];

@@ -143,6 +143,7 @@ struct Overrides {
   int64_t split2 = 0;  // three-pass 1-D: second-pass length
   bool levels = false;  // method=levels: the per-level global-memory method
   bool mfma = false;    // method=mfma: matrix-core radix-16 stages (N = 256)
+  int blk = 0;  // 2-D: intermediate in column blocks of blk columns (0: natural order)
   std::string a, b, row, col, single, colt;
 };
 
@@ -176,6 +177,12 @@ int parse_schedule(const char* s, Overrides* o) {
     } else if (key == "col3") {
       if (val != "0" && val != "1") return FFT_ERR_INVALID_ARGUMENT;
       o->col3 = val == "1";
+    } else if (key == "blk") {
+      if (val == "0") o->blk = 0;
+      else if (val == "8") o->blk = 8;
+      else if (val == "16") o->blk = 16;
+      else if (val == "32") o->blk = 32;
+      else return FFT_ERR_INVALID_ARGUMENT;
     } else if (key == "method") {
       if (val != "lds" && val != "levels" && val != "mfma") return FFT_ERR_INVALID_ARGUMENT;
       o->levels = val == "levels";
@@ -467,6 +474,50 @@ int build_schedule_inner(const int64_t* n, int64_t batch, int dims, int dtype, c
     if (batch > ((int64_t)1 << 40) / (R * C)) return FFT_ERR_UNSUPPORTED_SIZE;
     S.points = R * C * batch;
     const int lgR = ilog2_64(R);
+    if (ov.blk) {
+      // the intermediate in column blocks (row pass -> workspace, column
+      // pass -> out): every column tile then reads one contiguous block
+      if (ov.col3 == 1 || R < 2 || C < ov.blk || C % ov.blk) return FFT_ERR_INVALID_ARGUMENT;
+      PassSpec rw, cl;
+      int rc = choose(ov.row, ROLE_ROW, (int)C, dtype, 64, R * batch, &rw.v);
+      if (rc) return rc;
+      rc = choose(ov.col, ROLE_COL, (int)R, dtype, ov.blk, ov.blk, &cl.v);
+      if (rc) return rc;
+      const int64_t T = C / rw.v->P;  // lanes per row (C >= P for every row variant with C >= 8)
+      if (rw.v->P > C || T % ov.blk || ov.blk % cl.v->W || R * batch > INT32_MAX) return FFT_ERR_INVALID_ARGUMENT;
+      PassArgs& a = rw.args;
+      a.in_batch = a.out_batch = 0;
+      a.in_line = a.out_line = C;
+      a.in_elem = a.out_elem = 1;
+      a.lines = (int32_t)(R * batch);
+      a.tiles_per_batch = (int32_t)((R * batch + rw.v->W - 1) / rw.v->W);
+      a.total_tiles = a.tiles_per_batch;
+      a.blk_lg = ilog2_64(ov.blk);
+      a.blk_rows_lg = lgR;
+      rw.src = SEL_IN;
+      rw.dst = SEL_WS;
+      rw.first = true;
+      // column pass, per image: block j (R rows of blk columns, contiguous)
+      // is one "batch" of blk lines
+      PassArgs& b = cl.args;
+      b.in_batch = R * ov.blk;
+      b.out_batch = ov.blk;
+      b.in_line = b.out_line = 1;
+      b.in_elem = ov.blk;
+      b.out_elem = C;
+      b.lines = ov.blk;
+      b.tiles_per_batch = ov.blk / cl.v->W;
+      b.total_tiles = (int64_t)b.tiles_per_batch * (C / ov.blk);
+      cl.src = SEL_WS;
+      cl.dst = SEL_OUT;
+      cl.last = true;
+      cl.per_transform = true;
+      S.always_ws = true;
+      S.passes.push_back(rw);
+      S.passes.push_back(cl);
+      *out = S;
+      return FFT_OK;
+    }
     const bool three = ov.col3 == 1 ? true
                        : ov.col3 == 0 ? false
                                       : (lgR >= 12 && C >= 16);
@@ -756,6 +807,7 @@ struct ManyOptions {
   // and log2 of the first-pass length N1 of a two-pass transform (0 = the
   // default, ceil(L/2) capped at the longest tile)
   int passes_for[FFT_MAX_LOG2_1D + 1] = {};
+  int nt_store = 0;  // two-launch kernel: stores with the nontemporal hint
   int lg1_for[FFT_MAX_LOG2_1D + 1] = {};
 };
 
@@ -808,6 +860,9 @@ int parse_many_schedule(const char* s, ManyOptions* o) {
       if (v < 0 || v > 2) return FFT_ERR_INVALID_ARGUMENT;
       o->pipe = (int)v;
 
+    } else if (key == "ntst") {
+      if (v != 0 && v != 1) return FFT_ERR_INVALID_ARGUMENT;
+      o->nt_store = (int)v;
     } else if (key == "lag") {
       if (v < 0 || v > (1 << 24)) return FFT_ERR_INVALID_ARGUMENT;
       o->lag = (int)v;
@@ -1769,6 +1824,16 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
     }
     a.tw_img = mp.d_tw_img;
     a.tw_img_len = len;
+    // each launch of the two-launch kernel copies only the lengths it runs
+    a.tw_img_len_ph[0] = a.tw_img_len_ph[1] = len;
+    if (opt.pipe == 2) {
+      int mx[2] = {0, 0};
+      for (size_t i = 0; i < items.size(); ++i) {
+        const int ph = (int)i >= mb.q_off[1] ? 1 : 0;
+        mx[ph] = std::max(mx[ph], items[i].lg);
+      }
+      for (int ph = 0; ph < 2; ++ph) a.tw_img_len_ph[ph] = std::max(1, many_tw_image_prefix(opt.P, mx[ph]));
+    }
   }
   a.n_items = (int32_t)items.size();
   a.n_xforms = (int32_t)count;
@@ -1777,6 +1842,7 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
   a.q_off = mp.d_q_off;
   a.phase = 0;
   a.n_phase2 = opt.pipe == 2 ? mb.q_off[2] - mb.q_off[1] : 0;
+  a.nt_store = opt.nt_store;
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
   if (e != hipSuccess) {

@@ -246,6 +246,20 @@ void many_tw_map_lg(const int64_t* stage_off, int32_t tw_used, std::vector<int32
   }
 }
 
+template <int P, int LG = 1>
+int many_tw_prefix_of(int max_lg) {
+  if constexpr (LG > kManyMaxLg) {
+    return ManyTwOff<P, kManyMaxLg + 1>::value;
+  } else {
+    return max_lg < LG ? ManyTwOff<P, LG>::value : many_tw_prefix_of<P, LG + 1>(max_lg);
+  }
+}
+
+int many_tw_image_prefix(int P, int max_lg) {
+  if (P != 16) return 0;
+  return many_tw_prefix_of<16>(max_lg);
+}
+
 int many_tw_image_map(const int64_t* stage_off, int32_t tw_used, int P, int max_lg,
                       std::vector<int32_t>* map) {
   if (P != 16) return 0;
@@ -716,6 +730,23 @@ __device__ __forceinline__ void xprefetch(const ManyArgs& a, const ManyItemX& d,
     if (q < PP) pre.v[q] = load_c(p0 + q * step);
 }
 
+// Stores with the nontemporal hint (streamed: the caches need not keep them).
+__device__ __forceinline__ void store_nt(float2* p, float2 v) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  f2v r;
+  r.x = v.x;
+  r.y = v.y;
+  __builtin_nontemporal_store(r, reinterpret_cast<f2v*>(p));
+}
+__device__ __forceinline__ void store_nt(__half2* p, float2 v) {
+  const __half2 h = __halves2half2(__float2half_rn(v.x), __float2half_rn(v.y));
+  __builtin_nontemporal_store(*reinterpret_cast<const uint32_t*>(&h), reinterpret_cast<uint32_t*>(p));
+}
+__device__ __forceinline__ void store_nt(c16bf* p, float2 v) {
+  const uint32_t w = (uint32_t)f32_to_bf16(v.x) | ((uint32_t)f32_to_bf16(v.y) << 16);
+  __builtin_nontemporal_store(w, reinterpret_cast<uint32_t*>(p));
+}
+
 // Butterflies and epilogue of one item (its points in v, outputs left in v
 // in the store mapping, times the inter-pass twiddle and the scale,
 // conjugated back for the inverse).
@@ -772,7 +803,7 @@ __device__ __forceinline__ void xcompute(const ManyArgs& a, const ManyItemX& d, 
 
 // Stores of an item whose outputs xcompute left in v.  `base` is the lane's
 // line offset for one-pass items.
-template <int L, int P, int NT, typename TS>
+template <int L, int P, int NT, typename TS, bool NTST>
 __device__ __forceinline__ void xstore(const ManyArgs& a, const ManyItemX& d, const float2* v, int64_t base,
                                        int tid) {
   using S = Sched<L, P>;
@@ -801,8 +832,13 @@ __device__ __forceinline__ void xstore(const ManyArgs& a, const ManyItemX& d, co
     }
   }
   if (ok) {
+    if constexpr (NTST) {
 #pragma unroll
-    for (int q = 0; q < PP; ++q) store_c(dst + obase + (int64_t)(t + q * T) * oelem, v[q]);
+      for (int q = 0; q < PP; ++q) store_nt(dst + obase + (int64_t)(t + q * T) * oelem, v[q]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < PP; ++q) store_c(dst + obase + (int64_t)(t + q * T) * oelem, v[q]);
+    }
   }
 }
 
@@ -858,8 +894,8 @@ __device__ __forceinline__ int64_t xbase(const ManyArgs& a, const ManyItemX& d, 
 // iteration earlier: the pipelining does not depend on the compiler
 // computing exact wait counts across the many item paths.
 // Launch `a.phase` runs the items q_off[phase] .. q_off[phase+1]-1.
-template <typename TS, int P, int NT, int MAXLG>
-__global__ void __launch_bounds__(NT, 1) k_many_2l(ManyArgs a) {
+template <typename TS, int P, int NT, int MAXLG, bool NTST>
+__global__ void __launch_bounds__(NT, 512 / NT) k_many_2l(ManyArgs a) {
   static_assert(NT * P >= (1 << MAXLG) && MAXLG <= 12, "tile lengths 2 .. 2^12");
   constexpr int XN = many_lds_max<P, NT, MAXLG>();
   constexpr int TWN = many_tw_total<P, MAXLG>();
@@ -876,34 +912,34 @@ __global__ void __launch_bounds__(NT, 1) k_many_2l(ManyArgs a) {
   int* exits = heads + 8 + ph;
   constexpr int kNoClaim = 1 << 30;
 
-  // stage twiddles: one contiguous copy of the plan's LDS image
-  {
-    constexpr int K = (TWN + NT - 1) / NT;
-    float2 tmp[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (tid + k * NT < a.tw_img_len) tmp[k] = a.tw_img[tid + k * NT];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (tid + k * NT < a.tw_img_len) twl[tid + k * NT] = tmp[k];
-  }
-
   // first two claims
   if (tid == 0) {
     s_first[0] = lo + atomicAdd(head, 1);
     s_first[1] = lo + atomicAdd(head, 1);
   }
-  __syncthreads();  // stage twiddles and claims visible
+  __syncthreads();  // claims visible
   int c = min(s_first[0], hi);
   int n = min(s_first[1], hi);
   ManyItemX dc = xitem(a, c, hi);
   ManyItemX dn = xitem(a, n, hi);
-  XPre<P> pre;
   int64_t base_c = 0, base_n = 0;
-  if (c < hi) {
-    if (dc.kind == MANY_SINGLE) base_c = xbase<P>(a, dc, tid);
-    if (dc.lg >= 1) xprefetch<P, NT, TS>(a, dc, base_c, pre, tid);
-  }
+  if (c < hi && dc.kind == MANY_SINGLE) base_c = xbase<P>(a, dc, tid);
+
+  // stage twiddles: the prefix of the plan's LDS image that this launch's
+  // lengths read, loaded while the first item's loads are in flight (every
+  // lane loads an entry; entries past the prefix are not written)
+  constexpr int K = (TWN + NT - 1) / NT;
+  const int img = min(a.tw_img_len, a.tw_img_len_ph[ph]);
+  float2 tmp[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (k * NT < img) tmp[k] = a.tw_img[min(tid + k * NT, img - 1)];
+  XPre<P> pre;
+  if (c < hi && dc.lg >= 1) xprefetch<P, NT, TS>(a, dc, base_c, pre, tid);
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (tid + k * NT < img) twl[tid + k * NT] = tmp[k];
+  // (the barrier at the top of the first iteration makes them visible)
   if (n < hi && dn.kind == MANY_SINGLE) base_n = xbase<P>(a, dn, tid);
   int claim = kNoClaim;  // thread 0: raw value of the claim in flight
   if (tid == 0) claim = atomicAdd(head, 1);
@@ -920,7 +956,7 @@ __global__ void __launch_bounds__(NT, 1) k_many_2l(ManyArgs a) {
     vm_wait<0>();
     // stores of the previous item
     if (dp.kind >= 0) {
-      MANY_XCD_SWITCH(dp.lg, (xstore<L, P, NT, TS>(a, dp, v, base_p, tid)));
+      MANY_XCD_SWITCH(dp.lg, (xstore<L, P, NT, TS, NTST>(a, dp, v, base_p, tid)));
     }
 #pragma unroll
     for (int k = 0; k < P; ++k) v[k] = pre.v[k];
@@ -965,7 +1001,7 @@ __global__ void __launch_bounds__(NT, 1) k_many_2l(ManyArgs a) {
   }
   // the last item's stores
   if (dp.kind >= 0) {
-    MANY_XCD_SWITCH(dp.lg, (xstore<L, P, NT, TS>(a, dp, v, base_p, tid)));
+    MANY_XCD_SWITCH(dp.lg, (xstore<L, P, NT, TS, NTST>(a, dp, v, base_p, tid)));
   }
   // The last workgroup out resets this launch's queue head for the next exec.
   __syncthreads();
@@ -988,7 +1024,10 @@ hipError_t launch_many_2l(const ManyArgs& a, int grid, hipStream_t s) {
     ManyArgs b = a;
     b.phase = ph;
     if (ph == 1 && a.n_phase2 == 0) break;
-    hipLaunchKernelGGL((k_many_2l<TS, P, NT, MAXLG>), dim3(grid), dim3(NT), 0, s, b);
+    if (a.nt_store)
+      hipLaunchKernelGGL((k_many_2l<TS, P, NT, MAXLG, true>), dim3(grid), dim3(NT), 0, s, b);
+    else
+      hipLaunchKernelGGL((k_many_2l<TS, P, NT, MAXLG, false>), dim3(grid), dim3(NT), 0, s, b);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -998,9 +1037,11 @@ hipError_t launch_many_2l(const ManyArgs& a, int grid, hipStream_t s) {
 template <typename TS, int P, int NT, int MAXLG>
 int blocks_many_2l() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_many_2l<TS, P, NT, MAXLG>, NT, 0) != hipSuccess)
+  int n2 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_many_2l<TS, P, NT, MAXLG, false>, NT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n2, k_many_2l<TS, P, NT, MAXLG, true>, NT, 0) != hipSuccess)
     return 0;
-  return n;
+  return n < n2 ? n : n2;
 }
 
 template <typename TS, int P, int NT, int MAXLG>
@@ -1050,6 +1091,9 @@ static const ManyVariant kManyVariants[] = {
     MANY_PIPE(c16bf, DT_C16BF, 16, 256, 11),
     MANY_2L(float2, DT_C64, 16, 512, 12),        MANY_2L(__half2, DT_C16F, 16, 512, 12),
     MANY_2L(c16bf, DT_C16BF, 16, 512, 12),
+    // 256 lanes, tiles up to 2^11: half the LDS, two workgroups per CU
+    MANY_2L(float2, DT_C64, 16, 256, 11),        MANY_2L(__half2, DT_C16F, 16, 256, 11),
+    MANY_2L(c16bf, DT_C16BF, 16, 256, 11),
 };
 
 int many_variant_count() { return (int)(sizeof(kManyVariants) / sizeof(kManyVariants[0])); }

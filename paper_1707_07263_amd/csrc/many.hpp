@@ -81,6 +81,8 @@ struct ManyArgs {
   const ManyItemX* itx;
   const int32_t* q_off;
   int32_t phase, n_phase2;
+  int32_t nt_store;   // two-launch kernel: stores with the nontemporal hint
+  int32_t tw_img_len_ph[2];  // two-launch kernel: image entries each launch's lengths need
   int32_t* watchdog;  // flag set when a bounded wait expires
 };
 
@@ -105,6 +107,10 @@ struct ManyVariant {
 int many_tw_image_map(const int64_t* stage_off, int32_t tw_used, int P, int max_lg,
                       std::vector<int32_t>* map);
 hipError_t launch_gather_f2(float2* dst, const float2* src, const int32_t* map, int n, hipStream_t s);
+// Entries of the pipelined kernels' stage-twiddle image (P points per lane)
+// that tiles of length up to 2^max_lg read: the image holds the lengths in
+// increasing order, so this is a prefix.
+int many_tw_image_prefix(int P, int max_lg);
 
 // Compiled persistent-kernel variants (storage type x points per lane x
 // workgroup size).

@@ -176,7 +176,18 @@ def test_describe_three_pass_2d(lib):
     # narrower variant exists (8 columns: 8-column tiles, not 16)
     d = capi.fft_describe([4096, 8], 2, 2, capi.FFT_C64, "col3=1")
     assert d["passes"] == 3
-    assert all(int(nm.split("w")[1].rstrip("qx_c64")) <= 8 for nm in d["names"][:2]), d["names"]
+    assert all(int(re.search(r"w(\d+)", nm).group(1)) <= 8 for nm in d["names"][:2]), d["names"]
+
+
+def test_describe_blocked_2d(lib):
+    d = capi.fft_describe([4096, 4096], 1, 2, capi.FFT_C64, "blk=8")
+    assert d["passes"] == 2 and d["names"][0].startswith("r4096") and d["names"][1].startswith("c4096")
+    # a column tile never spans two blocks; a row lane must stay in one block column
+    assert int(re.search(r"w(\d+)", d["names"][1]).group(1)) <= 8
+    for shape, sched in (([64, 64], "blk=16"), ([16, 8], "blk=8"), ([4096, 4096], "blk=8;col3=1"),
+                         ([4096, 4096], "blk=12"), ([1, 4096], "blk=8")):
+        with pytest.raises(capi.FFTError):
+            capi.fft_describe(shape, 1, 2, capi.FFT_C64, sched)
 
 
 def test_describe_levels_method(lib):

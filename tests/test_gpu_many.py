@@ -77,7 +77,8 @@ def test_uneven_512_complex64(dev, which):
     assert np.all(per_transform_errors(inv, ref_inv, sizes) <= tol)
 
 
-@pytest.mark.parametrize("pipe", [None, "pipe=1;threads=512", "pipe=1;threads=256", "pipe=2;threads=512"])
+@pytest.mark.parametrize("pipe", [None, "pipe=1;threads=512", "pipe=1;threads=256", "pipe=2;threads=512",
+                                  "pipe=2;threads=256;ntst=1"])
 @pytest.mark.parametrize("dt", ["f16", "bf16"])
 def test_uneven_512_16bit(dev, dt, pipe):
     code, tname = DT16[dt]
@@ -111,6 +112,8 @@ def test_uneven_512_16bit(dev, dt, pipe):
                                       "pipe=1;threads=256;pass2=3", "pipe=2;threads=512",
                                       "pipe=2;threads=512;pass2=1", "pipe=2;threads=512;pass2=9",
                                       "pipe=2;threads=512;pass.11=2;pass.12=2;n1.16=6;n1.15=9;n1.14=7",
+                                      "pipe=2;threads=256", "pipe=2;threads=256;ntst=1;pass2=9",
+                                      "pipe=2;threads=512;ntst=1",
                                       "threads=512;n1.16=10;pass.9=2;n1.5=2"])
 def test_many_schedules_and_small_sizes(dev, schedule):
     # every length 2^0..2^16 twice, shuffled, under each compiled schedule
@@ -162,7 +165,8 @@ def test_many_inverse_scale_and_repeat(dev):
         capi.fft_destroy(h)
 
 
-@pytest.mark.parametrize("schedule", [None, "pipe=1;threads=512", "pipe=1;threads=256", "pipe=2;threads=512"])
+@pytest.mark.parametrize("schedule", [None, "pipe=1;threads=512", "pipe=1;threads=256", "pipe=2;threads=512",
+                                      "pipe=2;threads=256;ntst=1"])
 def test_many_graph_capture_replay(dev, schedule):
     sizes, packed = workloads.uneven_batch(128, 8, 16, seed=31)
     xt = to_gpu_c64(packed, dev)
@@ -255,7 +259,8 @@ def test_many_errors(dev):
     assert per_transform_errors(xt.cpu().numpy(), ref, np.array(sizes)).max() <= 1e-5
 
 
-@pytest.mark.parametrize("schedule", ["pipe=2;threads=512", "pipe=2;threads=512;pass2=9"])
+@pytest.mark.parametrize("schedule", ["pipe=2;threads=512", "pipe=2;threads=512;pass2=9",
+                                      "pipe=2;threads=256;ntst=1"])
 def test_many_two_launch_repeat_inverse_inplace(dev, schedule):
     # two launches per exec: repeated execs of one plan agree bitwise (each
     # launch resets its own queue head), the inverse with the default and a

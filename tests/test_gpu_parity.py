@@ -500,3 +500,23 @@ def test_batch_beyond_2p31_points(dev, n, b):
     err = rel_l2_rows(ys, oracle.fft(xs), n)
     print(f"n={n} batch={b}: sampled rows rel-L2 max {err.max():.3e}")
     assert err.max() <= tol_fp32(n), float(err.max())
+
+
+BLOCKED_2D = [((256, 512), 3, "blk=8"), ((1024, 1024), 2, "blk=8;xcd=01"), ((512, 4096), 1, "blk=8"),
+              ((4096, 256), 2, "blk=16"), ((128, 2048), 2, "blk=32"),
+              ((4096, 4096), 1, "blk=8;row=r4096p16w1q_c64;col=c4096p32w8x_c64;xcd=01")]
+
+
+@pytest.mark.parametrize("shape,batch,sched", BLOCKED_2D)
+@pytest.mark.parametrize("inverse", [False, True])
+def test_2d_blocked_intermediate(dev, shape, batch, sched, inverse):
+    # rows into column blocks of a workspace, then columns reading whole
+    # blocks: out of place and in place, against the oracle
+    r, c = shape
+    x = workloads.normal_batch(r * c, batch, seed=r + c + batch).reshape(batch, r, c)
+    got = run_c64(x, [r, c], inverse=inverse, schedule=sched, dev=dev)
+    ref = oracle.fft2(x.astype(np.complex64), inverse=inverse)
+    err = rel_l2_rows(got.reshape(batch, -1), ref.reshape(batch, -1), r * c)
+    assert err.max() <= tol_fp32(r * c), (shape, sched, float(err.max()))
+    got2 = run_c64(x, [r, c], inverse=inverse, schedule=sched, inplace=True, dev=dev)
+    assert np.array_equal(got, got2)
