@@ -141,18 +141,26 @@ int fft_plan_many(const int64_t *sizes, int64_t count, int dtype, int direction,
 /*
  * As fft_plan_many with a schedule string of ';'-separated items:
  *   'p=' 8|16          points per lane (radix of the in-register stages)
- *   'threads=' 256|512 workgroup size (not every dtype has every size)
+ *   'threads=' 256|512 workgroup size (not every dtype has every size;
+ *                      default 512)
  *   'pass2=' t         lengths of at least 2^t use two passes (1 <= t <= 1 +
  *                      log2 of the longest one-tile length, which is the default)
  *   'order=' bigfirst|given   order of the work queue
- *   'pipe=' 0|1|2      1: one workgroup per CU that loads its next item while
- *                      it transforms the current one (compiled for p=16,
- *                      threads=512), items assigned round-robin in queue order;
- *                      2: the same pipelining in two launches per exec
- *                      (first passes and one-pass tiles, then second passes;
- *                      the kernel boundary orders a transform's passes, no
- *                      workgroup waits for another), items claimed from each
- *                      launch's atomic queue head
+ *   'pipe=' 0|1|2      0: one launch, items from a shared atomic queue, a
+ *                      second-pass tile waits on its transform's completion
+ *                      counter; 1: one workgroup per CU that loads its next
+ *                      item while it transforms the current one (compiled for
+ *                      p=16, threads=256|512), items assigned round-robin in
+ *                      queue order, completion counters as in 0 -- its
+ *                      progress needs every workgroup of the launch resident
+ *                      at once, so it is only for a GPU the launch has to
+ *                      itself; 2 (the default): the same pipelining in two
+ *                      launches per exec (first passes and one-pass tiles,
+ *                      then second passes; the kernel boundary orders a
+ *                      transform's passes and no workgroup waits for another),
+ *                      items claimed from each launch's atomic queue head.
+ *                      fft_plan_info names the kernel many_queue, many_pipe
+ *                      or many_2launch
  *   'pass.L=' 1|2      length 2^L in one pass or two (one needs 2^L within
  *                      the longest tile)
  *   'n1.L=' l          two passes for length 2^L with a first pass of 2^l

@@ -24,6 +24,9 @@ class Plan:
         self.handle = handle
         self.kind = kind
         self.workspace = None  # torch tensor backing a caller-owned workspace
+        # batched plans whose kernel waits on completion counters (the
+        # two-launch kernel never waits)
+        self.waits = kind == "many" and capi.fft_plan_info(handle)["pass_variant"][0] != "many_2launch"
 
     def __del__(self):
         try:
@@ -172,6 +175,12 @@ def fft_many(packed: torch.Tensor, sizes, inverse: bool = False, *, scale=None,
     elif out.shape != packed.shape or out.dtype != packed.dtype or not out.is_contiguous():
         raise ValueError("out must be a contiguous tensor of the packed input's shape and dtype")
     plan.exec(packed, out)
+    if plan.waits:
+        # kernels whose second passes wait on completion counters: a wait that
+        # ran out (e.g. workgroups that were not resident) leaves wrong
+        # results, so read the flag (this synchronises)
+        if capi.fft_many_watchdog(plan.handle, clear=True) == capi.FFT_ERR_WATCHDOG:
+            raise RuntimeError("fft_many: a dependency wait expired; the results are invalid")
     return out
 
 

@@ -301,7 +301,7 @@ def tune_many(sizes, dtype=capi.FFT_C64, reps=10, verbose=False):
                 for pass2 in range(max(8, max_tile - 3), max_tile + 2):
                     for order in ("bigfirst", "given"):
                         grid.append(f"p={P};threads={threads};pass2={pass2};order={order}"
-                                    + (";pipe=1" if pipe else ""))
+                                    + (";pipe=1" if pipe else ";pipe=0"))
     # the two-launch kernel (512 lanes, tiles up to 2^12)
     for pass2 in range(9, 14):
         grid.append(f"p=16;threads=512;pipe=2;pass2={pass2}")

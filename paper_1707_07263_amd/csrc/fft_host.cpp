@@ -795,9 +795,12 @@ void many_free(ManyPlan& mp) {
 namespace {
 
 struct ManyOptions {
-  int P = 16, threads = 256, pass2 = 0;  // pass2 0: two passes above the longest one-tile length
+  int P = 16, threads = 512, pass2 = 0;  // pass2 0: two passes above the longest one-tile length
   bool given_order = false;
-  int pipe = 0;  // 1: the software-pipelined kernel (one workgroup per CU)
+  // 0: shared queue with completion counters; 1: software-pipelined, one
+  // workgroup per CU, round-robin items, completion counters; 2 (default):
+  // software-pipelined, two launches per exec, no waits
+  int pipe = 2;
   // 0: every first-pass tile ahead of every second-pass tile; k > 0: the
   // second-pass tiles of split transform i follow the first-pass tiles of
   // split transform i + k, so its intermediate is still in the last-level
@@ -1285,7 +1288,11 @@ int fft_plan_info(fft_plan_t p, fft_plan_info_t* info) {
   const double es = (double)esize(p->dtype);
   if (p->kind == 1) {
     info->passes = 1;
-    snprintf(info->pass_variant[0], 32, "%s", "persistent_many");
+    // the batched kernel: many_2launch (two launches, no waits), many_queue
+    // (shared queue, completion counters), many_pipe (round-robin items,
+    // completion counters)
+    const int pipe = p->many.var ? p->many.var->pipe : 0;
+    snprintf(info->pass_variant[0], 32, "%s", pipe == 2 ? "many_2launch" : pipe == 1 ? "many_pipe" : "many_queue");
     info->points = p->many.points;
     info->flops = p->many.flops;
     info->bytes_min = 2.0 * es * (double)p->many.points;

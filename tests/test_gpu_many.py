@@ -93,6 +93,7 @@ def test_uneven_512_16bit(dev, dt, pipe):
     try:
         capi.fft_exec(h, xt.data_ptr(), out.data_ptr(), torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
+        assert capi.fft_many_watchdog(h) == capi.FFT_OK  # no dependency wait ran out
     finally:
         capi.fft_destroy(h)
     got = from_gpu_16(out)
@@ -105,8 +106,10 @@ def test_uneven_512_16bit(dev, dt, pipe):
     print(f"512 uneven {dt} end-to-end vs unquantised input: max {e2e.max():.3e}")
 
 
-@pytest.mark.parametrize("schedule", [None, "p=8", "pass2=10", "pass2=13;order=given",
-                                      "threads=512", "pass2=1", "lag=1", "lag=3;pass2=9",
+@pytest.mark.parametrize("schedule", [None, "pipe=0;threads=256;p=8", "pipe=0;threads=256;pass2=10",
+                                      "pipe=0;threads=256;pass2=13;order=given", "pipe=0;threads=512",
+                                      "pipe=0;threads=256;pass2=1", "pipe=0;threads=256;lag=1",
+                                      "pipe=0;threads=256;lag=3;pass2=9",
                                       "pipe=1;threads=512", "pipe=1;threads=512;pass2=1",
                                       "pipe=1;threads=512;pass2=9;lag=2", "pipe=1;threads=256",
                                       "pipe=1;threads=256;pass2=3", "pipe=2;threads=512",
@@ -114,7 +117,7 @@ def test_uneven_512_16bit(dev, dt, pipe):
                                       "pipe=2;threads=512;pass.11=2;pass.12=2;n1.16=6;n1.15=9;n1.14=7",
                                       "pipe=2;threads=256", "pipe=2;threads=256;ntst=1;pass2=9",
                                       "pipe=2;threads=512;ntst=1",
-                                      "threads=512;n1.16=10;pass.9=2;n1.5=2"])
+                                      "pipe=0;threads=512;n1.16=10;pass.9=2;n1.5=2"])
 def test_many_schedules_and_small_sizes(dev, schedule):
     # every length 2^0..2^16 twice, shuffled, under each compiled schedule
     g = workloads.rng(77)
@@ -129,7 +132,8 @@ def test_many_schedules_and_small_sizes(dev, schedule):
     assert np.all(errs <= tol), (schedule, float((errs / tol).max()))
 
 
-@pytest.mark.parametrize("schedule", ["lag=0", "lag=2", "threads=512;lag=1", "pipe=1;threads=512",
+@pytest.mark.parametrize("schedule", ["pipe=0;threads=256;lag=0", "pipe=0;threads=256;lag=2",
+                                      "pipe=0;threads=512;lag=1", "pipe=1;threads=512",
                                       "pipe=1;threads=256", "pipe=2;threads=512"])
 def test_many_16x2p20_lagged_queue(dev, schedule):
     # sixteen 2^20-point transforms in one launch, second passes interleaved

@@ -81,9 +81,11 @@ def test_uneven_512_queue():
         simulate(items, ft, workers, rng)
 
 
-@pytest.mark.parametrize("schedule", [None, "p=8", "pass2=10", "pass2=13;order=given",
-                                      "threads=512", "pass2=1", "pass2=2;order=given",
-                                      "lag=1", "lag=3;pass2=9", "lag=100"])
+@pytest.mark.parametrize("schedule", [None, "pipe=0;threads=256;p=8", "pipe=0;threads=256;pass2=10",
+                                      "pipe=0;threads=256;pass2=13;order=given", "pipe=0;threads=512",
+                                      "pipe=0;threads=256;pass2=1", "pipe=0;threads=256;pass2=2;order=given",
+                                      "pipe=0;threads=256;lag=1", "pipe=0;threads=256;lag=3;pass2=9",
+                                      "pipe=0;threads=256;lag=100"])
 def test_queue_all_lengths(schedule):
     g = np.random.default_rng(5)
     sizes = np.array([1 << e for e in list(range(0, 17)) * 2])
@@ -104,7 +106,7 @@ def test_queue_errors():
             capi.fft_describe_many(sizes)
         assert ei.value.status == code
     for bad in ("p=7", "threads=100", "pass2=0", "pass2=14", "order=random", "x=1", "lag=-1",
-                "pipe=1;threads=256;pass2=13", "pipe=2"):
+                "pipe=1;threads=256;pass2=13", "pipe=3", "pipe=2;threads=512;p=8"):
         with pytest.raises(capi.FFTError) as ei:
             capi.fft_describe_many([256], schedule=bad)
         assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT, bad
@@ -114,7 +116,7 @@ def test_queue_lag_interleaves():
     # with lag k the second-pass tiles of split transform i come right after
     # the first-pass tiles of transform i + k
     sizes = [1 << 20] * 6
-    items, ft = check_queue(sizes, "lag=2")
+    items, ft = check_queue(sizes, "pipe=0;threads=256;lag=2")
     kinds = [(int(k), int(a)) for k, _, a, _ in items]
     runs = []
     for k, a in kinds:
@@ -246,4 +248,5 @@ def test_per_length_schedule_items():
     for bad in ("n1.16=13", "n1.16=3", "pass.13=1", "pass.9=3", "n1.0=1", "n1.x=2", "nx.9=2"):
         with pytest.raises(capi.FFTError):
             capi.fft_describe_many(sizes + [1 << 15, 1 << 13], capi.FFT_C64, bad)
-    assert len(capi.fft_describe_many_launches(sizes, capi.FFT_C64, None)) == 2
+    assert len(capi.fft_describe_many_launches(sizes, capi.FFT_C64, None)) == 3  # default: two launches
+    assert len(capi.fft_describe_many_launches(sizes, capi.FFT_C64, "pipe=0;threads=256")) == 2
