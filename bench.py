@@ -22,8 +22,9 @@ Other modes (used to make the rocprofv3 summaries under profiles/):
   --mode profile     run warmup + steps only (no CPU baseline), for
                      `rocprofv3 --kernel-trace --stats` and `--pmc` runs;
                      also runs one plain 256 MiB device copy (calibration);
-                     --profile-workload image2d|many profiles the 4096^2 image
-                     or the 512 uneven transforms instead of the step
+                     --profile-workload image2d|many|dft256 profiles the 4096^2
+                     image, the 512 uneven transforms or 65536 x 256 under each
+                     one-kernel 256-point method instead of the step
   --mode configs     every benchmarked workload (1024 single, 1024 x 32768,
                      16 x 2^20 forward and inverse, the 4096^2 image, the
                      512 uneven batch in three storage types, 64 x 2^16
@@ -65,11 +66,14 @@ COPY_BYTES = 256 << 20
 # each recorded event costs a few microseconds of queue time, which would
 # otherwise be charged to every step of the wall-clock rate
 PROFILE_EVERY = 5
+# one-kernel 256-point methods compared in the dft256 profile: the fastest
+# LDS butterfly variant, matrix-core stages, cross-lane exchanges
+DFT256_SCHEDULES = ("single=r256p8w8_c64", "method=mfma", "method=xlane", "method=xlane_bperm")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_fft_n2p20_b16.txt")
 
 
 # sources of other kernel families, which the benchmarked step never runs
-NOT_IN_STEP = ("many.", "levels.", "mfma.", "variants_c16.")
+NOT_IN_STEP = ("many.", "levels.", "mfma.", "xlane.", "variants_c16.")
 
 
 def kernel_source_hash() -> str:
@@ -103,11 +107,12 @@ def parse_args(argv=None):
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("DIR_FETCH", "DIR_WRITE"))
     ap.add_argument("--summarize-counters", metavar="DIR")
-    ap.add_argument("--profile-workload", choices=["step", "image2d", "many"], default="step",
+    ap.add_argument("--profile-workload", choices=["step", "image2d", "many", "dft256"], default="step",
                     help="profile mode: the benchmarked step, the 4096x4096 2-D image forward "
-                         "transform (tuned schedule, four rotating buffers), or the 512 uneven "
+                         "transform (tuned schedule, four rotating buffers), the 512 uneven "
                          "complex64 transforms in one persistent launch (tuned schedule, rotating "
-                         "buffers of >= 1 GiB)")
+                         "buffers of >= 1 GiB), or 65536 x 256 complex64 forward under each "
+                         "one-kernel 256-point method (LDS butterflies, matrix cores, cross-lane)")
     return ap.parse_args(argv)
 
 
@@ -677,14 +682,17 @@ def ablation(capi, torch, lds_plan, sets, nsets, stream, reps):
 
 
 def mfma_report(capi, torch, reps):
-    """256-point transforms: radix-16 stages as matrix-core products against
-    the fastest one-kernel butterfly variant for the same batch, with data
-    from HBM (65536 signals, rotating buffers) and resident in cache (2048
+    """256-point transforms: radix-16 stages as matrix-core products, and the
+    exchange between them as cross-lane moves (DPP/ds_swizzle, ds_bpermute),
+    against the fastest one-kernel butterfly variant for the same batch, with data
+    from HBM (65536 signals, rotating buffers), resident in the 256 MB
+    Infinity Cache (16384 signals, 64 MB in and out) and in L2 (2048
     signals, one buffer pair)."""
     names = [capi.fft_variant_name(i) for i in range(capi.fft_variant_count())]
     butterflies = [n for n in names if n.startswith("r256p") and n.endswith("_c64")]
     res = {}
-    for batch, label, rotate in ((65536, "hbm", True), (2048, "cache_resident", False)):
+    for batch, label, rotate in ((65536, "hbm", True), (16384, "infinity_cache_resident", False),
+                                 (2048, "cache_resident", False)):
         nb = batch * 256 * 8
         nsets = max(2, math.ceil(ROT_BYTES / (2 * nb))) if rotate else 1
         bufs = [(torch.randn(batch * 256, dtype=torch.complex64, device="cuda"),
@@ -706,12 +714,15 @@ def mfma_report(capi, torch, reps):
             return us
 
         best = min((timed(f"single={v}"), v) for v in butterflies)
-        mc = timed("method=mfma")
-        res[f"{batch}x256_{label}"] = {
-            "butterflies": {"us": round(best[0], 2), "variant": best[1], "GBps": round(2 * nb / (best[0] * 1e-6) / 1e9, 1),
-                            "of": len(butterflies)},
-            "matrix_cores": {"us": round(mc, 2), "variant": "mfma_dft256", "GBps": round(2 * nb / (mc * 1e-6) / 1e9, 1)},
-            "matrix_cores_over_butterflies_time": round(mc / best[0], 3)}
+        row = {"butterflies": {"us": round(best[0], 2), "variant": best[1],
+                               "GBps": round(2 * nb / (best[0] * 1e-6) / 1e9, 1), "of": len(butterflies)}}
+        for key, method, variant in (("matrix_cores", "mfma", "mfma_dft256"),
+                                     ("cross_lane_dpp", "xlane", "xlane_dft256"),
+                                     ("cross_lane_bpermute", "xlane_bperm", "xlane_bperm_dft256")):
+            t = timed(f"method={method}")
+            row[key] = {"us": round(t, 2), "variant": variant, "GBps": round(2 * nb / (t * 1e-6) / 1e9, 1)}
+            row[f"{key}_over_butterflies_time"] = round(t / best[0], 3)
+        res[f"{batch}x256_{label}"] = row
         del bufs
     return res
 
@@ -764,7 +775,7 @@ def main(argv=None) -> int:
         capi.fft_exec(fwd, xi.data_ptr(), yi.data_ptr(), stream)
         capi.fft_exec(inv, yi.data_ptr(), zi.data_ptr(), stream)
 
-    image_only = args.mode == "profile" and args.profile_workload in ("image2d", "many")
+    image_only = args.mode == "profile" and args.profile_workload in ("image2d", "many", "dft256")
     for i in range(0 if image_only else args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -814,6 +825,22 @@ def main(argv=None) -> int:
                 capi.fft_exec(hm, xi.data_ptr(), yi.data_ptr(), stream)
             torch.cuda.synchronize()
             capi.fft_destroy(hm)
+            del bufs
+        elif args.profile_workload == "dft256":
+            del sets
+            torch.cuda.empty_cache()
+            batch = 65536
+            nb = batch * 256 * 8
+            nd = max(2, math.ceil(ROT_BYTES / (2 * nb)))
+            bufs = [(torch.randn(batch * 256, dtype=torch.complex64, device=dev),
+                     torch.empty(batch * 256, dtype=torch.complex64, device=dev)) for _ in range(nd)]
+            for sched in DFT256_SCHEDULES:
+                hd = capi.fft_plan_ex([256], batch, 1, capi.FFT_C64, capi.FFT_FORWARD, sched)
+                for i in range(args.warmup + args.steps):
+                    xi, yi = bufs[i % nd]
+                    capi.fft_exec(hd, xi.data_ptr(), yi.data_ptr(), stream)
+                torch.cuda.synchronize()
+                capi.fft_destroy(hd)
             del bufs
         else:
             for i in range(args.steps):

@@ -116,7 +116,16 @@ int fft_plan(const int64_t *n, int64_t batch, int dims, int dtype, int direction
  *                                       through a plan-owned buffer of batch*N
  *                                       elements; in place as well, no workspace.
  *                                       fft_plan_info reports the whole sequence
- *                                       as one entry "levels_radix2".)
+ *                                       as one entry "levels_radix2".
+ *                                       'mfma', 'xlane', 'xlane_bperm': N = 256
+ *                                       complex64 only, 256 = 16 x 16 (eq. 5) in
+ *                                       one kernel, kept as experiments beside
+ *                                       the LDS path: the radix-16 stages as
+ *                                       matrix-core products ("mfma_dft256"), or
+ *                                       the exchange between the two stages as
+ *                                       cross-lane moves instead of LDS, by DPP
+ *                                       and ds_swizzle ("xlane_dft256") or by
+ *                                       ds_bpermute ("xlane_bperm_dft256").)
  *   variant  := name as listed by fft_variant_name()
  * FFT_ERR_INVALID_ARGUMENT if the string does not parse or names a variant
  * that cannot run this size.

@@ -24,6 +24,7 @@
 #include "levels.hpp"
 #include "many.hpp"
 #include "mfma.hpp"
+#include "xlane.hpp"
 #include "twiddle.hpp"
 #include "variants.hpp"
 
@@ -132,6 +133,9 @@ struct Schedule {
   bool levels = false;
   // 256-point transforms with matrix-core radix-16 stages (experiment)
   bool mfma = false;
+  // 256-point transforms whose exchange moves across lanes (experiment):
+  // 1 DPP and ds_swizzle, 2 ds_bpermute
+  int xlane = 0;
 };
 
 struct Overrides {
@@ -143,9 +147,15 @@ struct Overrides {
   int64_t split2 = 0;  // three-pass 1-D: second-pass length
   bool levels = false;  // method=levels: the per-level global-memory method
   bool mfma = false;    // method=mfma: matrix-core radix-16 stages (N = 256)
+  int xlane = 0;        // method=xlane (1) | xlane_bperm (2): cross-lane exchange (N = 256)
   int blk = 0;  // 2-D: intermediate in column blocks of blk columns (0: natural order)
   std::string a, b, row, col, single, colt;
 };
+
+// pass name of a single-launch 256-point experiment plan
+const char* dft256_name(const Schedule& S) {
+  return S.xlane == 2 ? "xlane_bperm_dft256" : S.xlane ? "xlane_dft256" : "mfma_dft256";
+}
 
 int parse_schedule(const char* s, Overrides* o) {
   if (!s) return FFT_OK;
@@ -184,9 +194,11 @@ int parse_schedule(const char* s, Overrides* o) {
       else if (val == "32") o->blk = 32;
       else return FFT_ERR_INVALID_ARGUMENT;
     } else if (key == "method") {
-      if (val != "lds" && val != "levels" && val != "mfma") return FFT_ERR_INVALID_ARGUMENT;
+      if (val != "lds" && val != "levels" && val != "mfma" && val != "xlane" && val != "xlane_bperm")
+        return FFT_ERR_INVALID_ARGUMENT;
       o->levels = val == "levels";
       o->mfma = val == "mfma";
+      o->xlane = val == "xlane" ? 1 : val == "xlane_bperm" ? 2 : 0;
     } else if (key == "colt") o->colt = val;
     else if (key == "a") o->a = val;
     else if (key == "b") o->b = val;
@@ -388,9 +400,10 @@ int build_schedule_inner(const int64_t* n, int64_t batch, int dims, int dtype, c
       *out = S;
       return FFT_OK;
     }
-    if (ov.mfma) {
+    if (ov.mfma || ov.xlane) {
       if (N != 256 || dtype != FFT_C64) return FFT_ERR_INVALID_ARGUMENT;
-      S.mfma = true;
+      S.mfma = ov.mfma;
+      S.xlane = ov.xlane;
       *out = S;
       return FFT_OK;
     }
@@ -468,7 +481,7 @@ int build_schedule_inner(const int64_t* n, int64_t batch, int dims, int dtype, c
     }
   } else {
     const int64_t R = n[0], C = n[1];
-    if (ov.levels || ov.mfma) return FFT_ERR_INVALID_ARGUMENT;  // 1-D only
+    if (ov.levels || ov.mfma || ov.xlane) return FFT_ERR_INVALID_ARGUMENT;  // 1-D only
     if (!pow2(R) || !pow2(C) || ilog2_64(R) > FFT_MAX_LOG2_2D || ilog2_64(C) > FFT_MAX_LOG2_2D)
       return FFT_ERR_UNSUPPORTED_SIZE;
     if (batch > ((int64_t)1 << 40) / (R * C)) return FFT_ERR_UNSUPPORTED_SIZE;
@@ -575,7 +588,7 @@ int build_schedule_inner(const int64_t* n, int64_t batch, int dims, int dtype, c
 }
 
 int apply_xcd(const std::string& mask, Schedule* S) {
-  if (S->levels || S->mfma) return mask == "0" || mask == "1" ? FFT_OK : FFT_ERR_INVALID_ARGUMENT;
+  if (S->levels || S->mfma || S->xlane) return mask == "0" || mask == "1" ? FFT_OK : FFT_ERR_INVALID_ARGUMENT;
   const size_t n = S->passes.size();
   if (mask.size() != 1 && mask.size() != n) return FFT_ERR_INVALID_ARGUMENT;
   for (size_t i = 0; i < n; ++i)
@@ -926,7 +939,7 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
   if (rc) return rc;
   fft_plan_s* p = new (std::nothrow) fft_plan_s();
   if (!p) return FFT_ERR_NO_MEMORY;
-  p->kind = S.levels ? 2 : S.mfma ? 3 : 0;
+  p->kind = S.levels ? 2 : (S.mfma || S.xlane) ? 3 : 0;
   p->dims = dims;
   p->n[0] = n[0];
   p->n[1] = dims == 2 ? n[1] : 1;
@@ -961,7 +974,7 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
     }
   }
   if (S.levels) tb.add(n[0] / 2, 0, n[0], 1);  // W_N^m, m < N/2
-  if (S.mfma) tb.add(256, 0, 256, 1);          // W_256^m, m < 256
+  if (S.mfma || S.xlane) tb.add(256, 0, 256, 1);          // W_256^m, m < 256
   const bool on_gpu = dims == 1 && ilog2_64(n[0]) >= kGpuTwiddleMinLog2;
   rc = upload_tables(p, tb, on_gpu);
   if (rc) {
@@ -1142,7 +1155,10 @@ int exec_impl(fft_plan_t p, const void* in, void* out, void* stream, void* ws_ov
     if (slot) hipEventRecord(slot[0], s);
     const bool inv = p->direction > 0;
     const float sc = p->scale_user ? (float)p->scale : (inv ? 1.0f / 256.0f : 1.0f);
-    hipError_t e = launch_dft256_mfma(in, out, p->batch, p->d_tables, sc, inv ? 1 : 0, inv ? 1 : 0, s);
+    hipError_t e =
+        p->sched.xlane
+            ? launch_dft256_xlane(in, out, p->batch, p->d_tables, sc, inv ? 1 : 0, inv ? 1 : 0, p->sched.xlane - 1, s)
+            : launch_dft256_mfma(in, out, p->batch, p->d_tables, sc, inv ? 1 : 0, inv ? 1 : 0, s);
     if (slot) hipEventRecord(slot[1], s);
     if (e != hipSuccess) return hip_fail(e);
     prof_commit(p, s);
@@ -1302,7 +1318,7 @@ int fft_plan_info(fft_plan_t p, fft_plan_info_t* info) {
   const Schedule& S = p->sched;
   if (p->kind == 3) {
     info->passes = 1;
-    snprintf(info->pass_variant[0], 32, "%s", "mfma_dft256");
+    snprintf(info->pass_variant[0], 32, "%s", dft256_name(S));
     info->points = S.points;
     info->flops = 5.0 * 256.0 * 8.0 * (double)p->batch;
     info->bytes_min = 2.0 * es * (double)S.points;
@@ -1386,12 +1402,12 @@ int fft_describe(const int64_t* n, int64_t batch, int dims, int dtype, const cha
   Schedule S;
   int rc = build_schedule(n, batch, dims, dtype, schedule, &S);
   if (rc) return rc;
-  if (passes) *passes = (S.levels || S.mfma) ? 1 : (int)S.passes.size();
+  if (passes) *passes = (S.levels || S.mfma || S.xlane) ? 1 : (int)S.passes.size();
   if (names)
     for (size_t i = 0; i < 4; ++i)
       snprintf(names[i], 32, "%s",
                S.levels ? (i == 0 ? "levels_radix2" : "")
-               : S.mfma ? (i == 0 ? "mfma_dft256" : "")
+               : (S.mfma || S.xlane) ? (i == 0 ? dft256_name(S) : "")
                         : i < S.passes.size() ? (S.passes[i].v ? S.passes[i].v->name : "copy_scale") : "");
   if (split) {
     split[0] = S.split[0];

@@ -202,6 +202,19 @@ def test_describe_levels_method(lib):
         assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT
 
 
+def test_describe_dft256_experiments(lib):
+    for method, name in (("mfma", "mfma_dft256"), ("xlane", "xlane_dft256"),
+                         ("xlane_bperm", "xlane_bperm_dft256")):
+        d = capi.fft_describe([256], 5, 1, capi.FFT_C64, f"method={method}")
+        assert d["passes"] == 1 and d["names"][0] == name
+        # 256-point complex64 batches only
+        for n, dims, dt in (([512], 1, capi.FFT_C64), ([256], 1, capi.FFT_C16F),
+                            ([16, 16], 2, capi.FFT_C64)):
+            with pytest.raises(capi.FFTError) as ei:
+                capi.fft_describe(n, 1, dims, dt, f"method={method}")
+            assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT
+
+
 def test_describe_xcd_masks(lib):
     for ok in ("xcd=0", "xcd=1", "xcd=01", "xcd=10"):
         assert capi.fft_describe([1 << 20], 16, 1, capi.FFT_C64, ok)["passes"] == 2
