@@ -208,16 +208,18 @@ def summarize_counters(d: str) -> str:
 def variant_kernel_signature(variant: str) -> str:
     """Template arguments of the strip kernel a variant name stands for, as
     rocprofv3 prints them (e.g. a1024p32w16x_c64 ->
-    k_strip<1024, 32, 16, 1, 0, true, 1, HIP_vector_type<float, 2u> >)."""
+    k_strip<1024, 32, 16, 1, 0, true, 1, HIP_vector_type<float, 2u> >,
+    a1024p32w16q2_c64 -> k_pipe<1024, 32, 16, 1, 0, true, 0, HIP_vector_type<float, 2u>, 2>)."""
     import re
-    m = re.match(r"([rac])(\d+)p(\d+)w(\d+)(q?)(x?)_(c64|f16|bf16)$", variant)
+    m = re.match(r"([rac])(\d+)p(\d+)w(\d+)(q2|q)?(x?)_(c64|f16|bf16)$", variant)
     if not m:
         return variant
     role, L, P, W, q, x, dt = m.groups()
     lm, sm, tw = {"r": (0, 0, "false"), "a": (1, 0, "true"), "c": (1, 1, "false")}[role]
     ts = {"c64": "HIP_vector_type<float, 2u>", "f16": "__half2", "bf16": "mfft::c16bf"}[dt]
-    kern = "k_pipe" if q else "k_strip"
-    return f"{kern}<{L}, {P}, {W}, {lm}, {sm}, {tw}, {1 if x else 0}, {ts} >"
+    if q:
+        return f"k_pipe<{L}, {P}, {W}, {lm}, {sm}, {tw}, {1 if x else 0}, {ts}, {2 if q == 'q2' else 1}>"
+    return f"k_strip<{L}, {P}, {W}, {lm}, {sm}, {tw}, {1 if x else 0}, {ts} >"
 
 
 def read_traffic(kernel_name: str):

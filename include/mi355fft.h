@@ -319,7 +319,12 @@ int fft_last_hip_error(void);
  * fft_variant_name(i) gives the i-th name (NULL if out of range) and
  * fft_variant_describe(i, ...) its sub-transform length L, points per lane
  * P, transforms per workgroup W, workgroup size and role (0 contiguous rows,
- * 1 first pass of a split, 2 strided columns).
+ * 1 first pass of a split, 2 strided columns, 3 strided columns with a
+ * twiddle).  Names read <role><L>p<P>w<W>[q|q2][x]_<dtype>: role r, a, c, t
+ * as above; q a persistent kernel (one workgroup per CU walking the tiles)
+ * with the next tile's loads in flight while one is computed, q2 with the
+ * next two; x the exchange through LDS in two rounds (real, then
+ * imaginary parts), which halves its LDS footprint.
  */
 int fft_variant_count(void);
 const char *fft_variant_name(int index);
@@ -336,9 +341,13 @@ int fft_describe(const int64_t *n, int64_t batch, int dims, int dtype,
                  int64_t split[2]);
 
 /*
- * Per-launch timing with HIP events recorded on the exec stream around each
- * kernel (timing-only events, recorded without a system-scope fence so that
- * they do not write back and invalidate caches between passes).
+ * Per-launch timing with HIP events on the exec stream (timing-only events,
+ * without a system-scope fence, so that they do not write back and
+ * invalidate caches between passes).  A pass that is one kernel launch
+ * hands its two events to the launch itself (hipExtLaunchKernel), so they
+ * take the kernel's own start and end, as a kernel trace does; other work
+ * (a copy pass, a pass launched once per transform, the batched, per-level
+ * and 256-point plans) is bracketed by events recorded before and after it.
  * fft_profile_enable(plan, slots) with slots >= 1 creates events for
  * `slots` execs (blocking) and clears the totals; every later fft_exec
  * records its launches into the next slot (a ring: execs beyond `slots`

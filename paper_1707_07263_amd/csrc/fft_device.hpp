@@ -519,12 +519,16 @@ k_strip(PassArgs a) {
 // ---------------------------------------------------------------------------
 // Persistent, software-pipelined strip pass.  One workgroup per CU walks the
 // tiles tile = blockIdx.x, + gridDim.x, ...; while it computes and stores one
-// tile, the loads of its next tile (data, and for the split's first pass the
-// twiddle inputs) are already in flight, so memory transfer overlaps the
-// butterflies instead of alternating with them.  Everything read between
-// issuing a prefetch and consuming it comes from LDS (the stage twiddles are
-// copied there once), since waiting on any later global load would also wait
-// for the prefetch.  Same lane mappings, stages and outputs as k_strip.
+// tile, the loads of its next DEPTH tiles (data, and for the split's first
+// pass the twiddle inputs) are already in flight, so memory transfer
+// overlaps the butterflies instead of alternating with them.  With DEPTH 2
+// the loads of two tiles are in flight at every point of the walk, which
+// keeps the memory system busy through a tile's compute and stores as well
+// (the first pass has only a few tiles per CU, so the ramp at the start and
+// the drain at the end weigh).  Everything read between issuing a prefetch
+// and consuming it comes from LDS (the stage twiddles are copied there
+// once), since waiting on any later global load would also wait for the
+// prefetch.  Same lane mappings, stages and outputs as k_strip.
 // ---------------------------------------------------------------------------
 template <int L, int P, int W, int EX, bool TWID>
 __host__ __device__ constexpr int pipe_lds_entries() {
@@ -532,9 +536,10 @@ __host__ __device__ constexpr int pipe_lds_entries() {
          (TWID ? W * Sched<L, P>::PP : 0);
 }
 
-template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS>
+template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS, int DEPTH>
 __global__ void __launch_bounds__((W * Sched<L, P>::T), 1)
 k_pipe(PassArgs a) {
+  static_assert(DEPTH == 1 || DEPTH == 2, "one or two tiles in flight");
   using S = Sched<L, P>;
   using LY = LdsLayout<L>;
   constexpr int T = S::T;
@@ -564,12 +569,17 @@ k_pipe(PassArgs a) {
 
   TwLds<L, P>::copy(twl, a.tw, tid, NT);
 
-  // registers of the prefetched tile; 16-bit pairs stay in their storage
-  // type (one register each) until they are converted at the top of the loop
+  // registers of a prefetched tile; 16-bit pairs stay in their storage type
+  // (one register each) until they are converted when the tile is consumed.
+  // A tile's W*PP step-row entries are held KR per lane.
   using PreT = typename std::conditional<sizeof(TS) == 8, float2, TS>::type;
-  PreT vn[PP];
-  float2 rown = make_float2(1.f, 0.f), lon = make_float2(1.f, 0.f), hin = make_float2(1.f, 0.f);
-  auto prefetch = [&](int64_t tl) {
+  constexpr int KR = TWID ? (W * PP + NT - 1) / NT : 1;
+  struct Pre {
+    PreT v[PP];
+    float2 row[KR];
+    float2 lo, hi;
+  };
+  auto prefetch = [&](Pre& n, int64_t tl) {
     const int64_t bat = tl / a.tiles_per_batch;
     const int line0 = (int)(tl - bat * a.tiles_per_batch) * W;
     const int tib = (int)(tl - bat * a.tiles_per_batch);
@@ -581,51 +591,53 @@ k_pipe(PassArgs a) {
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
       if constexpr (kStreamLoads<LOADM, W, TS>())
-        vn[q] = load_stream(reinterpret_cast<const float2*>(src + q * step));
+        n.v[q] = load_stream(reinterpret_cast<const float2*>(src + q * step));
       else if constexpr (sizeof(TS) == 8)
-        vn[q] = load_c(src + q * step);
+        n.v[q] = load_c(src + q * step);
       else
-        vn[q] = src[q * step];
+        n.v[q] = src[q * step];
     }
     if (TWID) {
-      // this tile's step rows W_N^{row*q*T} (one entry per lane) and the
-      // lane's base W_N^{row*t}, row = line >> tw_line_shift
-      if (W * PP == NT || tid < W * PP)
-        rown = a.tw_step[(int64_t)((uint32_t)min(line0 + tid / PP, a.lines - 1) >> a.tw_line_shift) * PP +
-                         (tid % PP)];
+      // this tile's step rows W_N^{row*q*T} and the lane's base W_N^{row*t},
+      // row = line >> tw_line_shift
+#pragma unroll
+      for (int j = 0; j < KR; ++j) {
+        const int e = tid + j * NT;
+        if (W * PP == KR * NT || e < W * PP)
+          n.row[j] = a.tw_step[(int64_t)((uint32_t)min(line0 + e / PP, a.lines - 1) >> a.tw_line_shift) * PP +
+                               (e % PP)];
+      }
       const uint32_t jb = ((uint32_t)min(line0 + m_st, a.lines - 1) >> a.tw_line_shift) * (uint32_t)t_st;
-      lon = a.tw_lo[jb & (uint32_t)a.tw_mask];
-      hin = a.tw_hi[jb >> a.tw_shift];
+      n.lo = a.tw_lo[jb & (uint32_t)a.tw_mask];
+      n.hi = a.tw_hi[jb >> a.tw_shift];
     }
   };
-  static_assert(!TWID || W * PP <= NT, "one step-row entry per lane");
 
-  // with the XCD remap, the workgroups of one XCD start on consecutive
-  // tiles, so that neighbouring strips, which share cache lines when a row
-  // segment is narrower than a line, are in flight on one L2 together
-  int64_t tile = tile_of(blockIdx.x, gridDim.x, a.xcd_remap);
-  if (tile < a.total_tiles) prefetch(tile);
-  lds_barrier();  // stage twiddles visible
-  for (; tile < a.total_tiles; tile += gridDim.x) {
+  // one tile: consume the registers prefetched for it, refill them with the
+  // tile `ahead` (if any), then butterflies, twiddle and stores
+  auto body = [&](Pre& n, int64_t tile, int64_t ahead) {
     lanes();
     float2 v[PP];
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
       if constexpr (sizeof(TS) == 8)
-        v[q] = vn[q];
+        v[q] = n.v[q];
       else
-        v[q] = load_c(&vn[q]);
+        v[q] = load_c(&n.v[q]);
       v[q].y = __uint_as_float(__float_as_uint(v[q].y) ^ sgn_in);
     }
     float2 tw_base = make_float2(1.f, 0.f);
     if (TWID) {
-      if (W * PP == NT || tid < W * PP) rowl[tid] = rown;
-      tw_base = cmul(hin, lon);
+#pragma unroll
+      for (int j = 0; j < KR; ++j) {
+        const int e = tid + j * NT;
+        if (W * PP == KR * NT || e < W * PP) rowl[e] = n.row[j];
+      }
+      tw_base = cmul(n.hi, n.lo);
     }
     const int64_t bat = tile / a.tiles_per_batch;
     const int line0 = (int)(tile - bat * a.tiles_per_batch) * W;
-    const int64_t next = tile + gridDim.x;
-    if (next < a.total_tiles) prefetch(next);
+    if (ahead < a.total_tiles) prefetch(n, ahead);
 
     int m = m_ld, t = t_ld;
     run_stages<L, P, W, EX, 1>(v, xch, m, t, m_st, t_st, LOADM != STOREM, twl);
@@ -638,7 +650,7 @@ k_pipe(PassArgs a) {
     // computed exactly its result (same data, same twiddles, same order of
     // operations): they store it over the last line, the same bits.  Every
     // lane stores, so the number of memory operations after the prefetch is
-    // the same on every path and the top of the loop waits for the prefetch
+    // the same on every path and the next tile waits for its own prefetch
     // only, not for these stores.
     const int line_st = lmap ? line : min(line, a.lines - 1);
     TS* dst = reinterpret_cast<TS*>(a.out) + bat * a.out_batch + (int64_t)line_st * a.out_line +
@@ -657,6 +669,29 @@ k_pipe(PassArgs a) {
       store_c(dst + q * step, y);
     }
     lds_barrier();  // LDS reads of this tile done before the next one overwrites
+  };
+
+  // with the XCD remap, the workgroups of one XCD start on consecutive
+  // tiles, so that neighbouring strips, which share cache lines when a row
+  // segment is narrower than a line, are in flight on one L2 together
+  const int64_t G = gridDim.x;
+  int64_t tile = tile_of(blockIdx.x, G, a.xcd_remap);
+  if constexpr (DEPTH == 1) {
+    Pre pa;
+    if (tile < a.total_tiles) prefetch(pa, tile);
+    lds_barrier();  // stage twiddles visible
+    for (; tile < a.total_tiles; tile += G) body(pa, tile, tile + G);
+  } else {
+    // two register sets alternate: the walk is unrolled by two so that each
+    // set keeps fixed registers
+    Pre pa, pb;
+    if (tile < a.total_tiles) prefetch(pa, tile);
+    if (tile + G < a.total_tiles) prefetch(pb, tile + G);
+    lds_barrier();  // stage twiddles visible
+    for (; tile < a.total_tiles; tile += 2 * G) {
+      body(pa, tile, tile + 2 * G);
+      if (tile + G < a.total_tiles) body(pb, tile + G, tile + 3 * G);
+    }
   }
 }
 

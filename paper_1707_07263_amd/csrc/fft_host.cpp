@@ -1207,7 +1207,10 @@ int exec_impl(fft_plan_t p, const void* in, void* out, void* stream, void* ws_ov
       src = ws ? (i == 0 ? (void*)in : ws) : (ps.src == SEL_IN ? (void*)in : out);
       dst = ws ? (i == 0 ? ws : out) : out;
     }
-    if (slot) hipEventRecord(slot[2 * i], s);
+    // a single kernel launch takes the events itself (its own start and end
+    // times); a copy or a per-transform loop is bracketed by markers
+    const bool one_launch = ps.v && !(ps.per_transform && p->batch > 1);
+    if (slot && !one_launch) hipEventRecord(slot[2 * i], s);
     hipError_t e;
     if (!ps.v) {
       e = launch_scale_copy(p->dtype, src, dst, ps.copy_n, (float)p->scale, s);
@@ -1228,13 +1231,13 @@ int exec_impl(fft_plan_t p, const void* in, void* out, void* stream, void* ws_ov
         for (int64_t b = 0; b < p->batch && e == hipSuccess; ++b) {
           a.in = (const char*)src + b * step;
           a.out = (char*)dst + b * step;
-          e = ps.v->launch(a, s);
+          e = ps.v->launch(a, s, nullptr, nullptr);
         }
       } else {
-        e = ps.v->launch(a, s);
+        e = ps.v->launch(a, s, slot ? slot[2 * i] : nullptr, slot ? slot[2 * i + 1] : nullptr);
       }
     }
-    if (slot) hipEventRecord(slot[2 * i + 1], s);
+    if (slot && !one_launch) hipEventRecord(slot[2 * i + 1], s);
     if (e != hipSuccess) return hip_fail(e);
   }
   prof_commit(p, s);

@@ -139,13 +139,15 @@ def c16_set():
     # the split passes of 2^16 and 2^20 with the next tile prefetched (a
     # sixth entry 1: persistent; the prefetch holds 16-bit pairs, one register
     # each) or 128 B row segments (32 pairs per row)
-    out += [("a", 1024, 32, 16, 0, 1), ("c", 1024, 32, 16, 1, 1),
+    out += [("a", 1024, 32, 16, 0, 1), ("a", 1024, 32, 16, 0, 2), ("c", 1024, 32, 16, 1, 1),
             ("a", 256, 16, 32, 0, 1), ("c", 256, 16, 32, 0, 1), ("c", 256, 16, 32, 0)]
     return list(dict.fromkeys(out))
 
 
 def name(role, L, P, W, ex, dt, persist=0):
-    return f"{role}{L}p{min(P, L)}w{W}{'q' if persist else ''}{'x' if ex else ''}_{dt}"
+    # q: persistent with the next tile in flight; q2: the next two tiles
+    q = {0: "", 1: "q", 2: "q2"}[persist]
+    return f"{role}{L}p{min(P, L)}w{W}{q}{'x' if ex else ''}_{dt}"
 
 
 def pipe_lds_bytes(L, P, W, ex, twid):
@@ -178,7 +180,8 @@ def pipe_set():
                         t = threads(L, P, W)
                         if t < 256 or t > 512:
                             continue
-                        if role == "a" and W * min(P, L) > t:
+                        # the first pass's step rows: at most two entries per lane
+                        if role == "a" and W * min(P, L) > 2 * t:
                             continue
                         if pipe_lds_bytes(L, P, W, ex, role == "a") > LDS_MAX:
                             continue
@@ -235,8 +238,11 @@ def main():
     for dt in ("f16", "bf16"):
         items += [v[:5] + (dt,) + v[5:] for v in c16_set()]
     emit("variants_c16.hip", "add_variants_c16", items)
+    # the first passes also with two tiles in flight
+    pipe = [v + ("c64", 1) for v in pipe_set()]
+    pipe += [v + ("c64", 2) for v in pipe_set() if v[0] == "a"]
     emit("variants_c64_pipe.hip", "add_variants_c64_pipe",
-         [v + ("c64", 1) for v in pipe_set()] + [("t",) + v + ("c64",) for v in coltw_set()])
+         pipe + [("t",) + v + ("c64",) for v in coltw_set()])
 
 
 if __name__ == "__main__":

@@ -3,6 +3,7 @@
 // per workgroup W, lane mappings, inter-pass twiddle on/off, storage type).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -13,7 +14,9 @@ namespace mfft {
 enum Role { ROLE_ROW = 0, ROLE_SPLIT_A = 1, ROLE_COL = 2, ROLE_COL_TW = 3 };
 enum Dtype { DT_C64 = 0, DT_C16F = 1, DT_C16BF = 2 };
 
-using LaunchFn = hipError_t (*)(const PassArgs&, hipStream_t);
+// start/stop: events (or null) that take the kernel's own start and end
+// times, from its dispatch packet rather than from queue markers around it
+using LaunchFn = hipError_t (*)(const PassArgs&, hipStream_t, hipEvent_t start, hipEvent_t stop);
 
 struct Variant {
   const char* name;
@@ -21,31 +24,33 @@ struct Variant {
   int lds_bytes;
   int tw_entries;  // stage-table entries for this (L, P)
   int ex;          // LDS exchange: 0 = (re, im) pairs, 1 = real then imaginary
-  int persistent;  // 1: k_pipe (grid = resident workgroups, tiles walked in a loop)
+  int persistent;  // k_pipe (grid = resident workgroups, tiles walked in a loop) with
+                   // 1 or 2 tiles' loads in flight; 0: k_strip
   LaunchFn launch;
   int (*blocks_per_cu)();  // persistent variants: resident workgroups per CU
 };
 
 template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS>
-hipError_t launch_strip(const PassArgs& a, hipStream_t s) {
+hipError_t launch_strip(const PassArgs& a, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   constexpr int NT = W * Sched<L, P>::T;
-  hipLaunchKernelGGL((k_strip<L, P, W, LOADM, STOREM, TWID, EX, TS>), dim3((unsigned)a.total_tiles),
-                     dim3(NT), 0, s, a);
+  hipExtLaunchKernelGGL((k_strip<L, P, W, LOADM, STOREM, TWID, EX, TS>), dim3((unsigned)a.total_tiles),
+                        dim3(NT), 0, s, start, stop, 0, a);
   return hipGetLastError();
 }
 
-template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS>
-hipError_t launch_pipe(const PassArgs& a, hipStream_t s) {
+template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS, int DEPTH>
+hipError_t launch_pipe(const PassArgs& a, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   constexpr int NT = W * Sched<L, P>::T;
   const unsigned grid = (unsigned)(a.grid > 0 ? a.grid : a.total_tiles);
-  hipLaunchKernelGGL((k_pipe<L, P, W, LOADM, STOREM, TWID, EX, TS>), dim3(grid), dim3(NT), 0, s, a);
+  hipExtLaunchKernelGGL((k_pipe<L, P, W, LOADM, STOREM, TWID, EX, TS, DEPTH>), dim3(grid), dim3(NT), 0, s,
+                        start, stop, 0, a);
   return hipGetLastError();
 }
 
-template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS>
+template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS, int DEPTH>
 int blocks_pipe() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pipe<L, P, W, LOADM, STOREM, TWID, EX, TS>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pipe<L, P, W, LOADM, STOREM, TWID, EX, TS, DEPTH>,
                                                    W * Sched<L, P>::T, 0) != hipSuccess)
     return 0;
   return n;
@@ -73,9 +78,10 @@ Variant make_variant(const char* name) {
   v.ex = EX;
   v.persistent = PERSIST;
   if constexpr (PERSIST) {
+    // PERSIST = tiles in flight while one is computed (1 or 2)
     v.lds_bytes = pipe_lds_entries<L, P, W, EX, TWID>() * 8;
-    v.launch = &launch_pipe<L, P, W, LOADM, STOREM, TWID, EX, TS>;
-    v.blocks_per_cu = &blocks_pipe<L, P, W, LOADM, STOREM, TWID, EX, TS>;
+    v.launch = &launch_pipe<L, P, W, LOADM, STOREM, TWID, EX, TS, PERSIST>;
+    v.blocks_per_cu = &blocks_pipe<L, P, W, LOADM, STOREM, TWID, EX, TS, PERSIST>;
   } else {
     v.lds_bytes = W * LdsLayout<L>::LS * (EX == 0 ? 8 : 4);
     v.launch = &launch_strip<L, P, W, LOADM, STOREM, TWID, EX, TS>;

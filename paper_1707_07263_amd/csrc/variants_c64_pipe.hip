@@ -7,6 +7,8 @@ void add_variants_c64_pipe(void (*add)(const Variant&)) {
   add(make_variant<ROLE_SPLIT_A, 256, 16, 32, 0, float2, 1>("a256p16w32q_c64"));
   add(make_variant<ROLE_SPLIT_A, 512, 16, 8, 0, float2, 1>("a512p16w8q_c64"));
   add(make_variant<ROLE_SPLIT_A, 512, 16, 16, 0, float2, 1>("a512p16w16q_c64"));
+  add(make_variant<ROLE_SPLIT_A, 512, 32, 16, 0, float2, 1>("a512p32w16q_c64"));
+  add(make_variant<ROLE_SPLIT_A, 512, 32, 32, 0, float2, 1>("a512p32w32q_c64"));
   add(make_variant<ROLE_SPLIT_A, 1024, 16, 8, 0, float2, 1>("a1024p16w8q_c64"));
   add(make_variant<ROLE_SPLIT_A, 1024, 32, 8, 0, float2, 1>("a1024p32w8q_c64"));
   add(make_variant<ROLE_SPLIT_A, 1024, 32, 16, 0, float2, 1>("a1024p32w16q_c64"));
@@ -26,6 +28,15 @@ void add_variants_c64_pipe(void (*add)(const Variant&)) {
   add(make_variant<ROLE_ROW, 2048, 16, 4, 0, float2, 1>("r2048p16w4q_c64"));
   add(make_variant<ROLE_ROW, 4096, 16, 1, 0, float2, 1>("r4096p16w1q_c64"));
   add(make_variant<ROLE_ROW, 4096, 16, 2, 0, float2, 1>("r4096p16w2q_c64"));
+  add(make_variant<ROLE_SPLIT_A, 256, 16, 16, 0, float2, 2>("a256p16w16q2_c64"));
+  add(make_variant<ROLE_SPLIT_A, 256, 16, 32, 0, float2, 2>("a256p16w32q2_c64"));
+  add(make_variant<ROLE_SPLIT_A, 512, 16, 8, 0, float2, 2>("a512p16w8q2_c64"));
+  add(make_variant<ROLE_SPLIT_A, 512, 16, 16, 0, float2, 2>("a512p16w16q2_c64"));
+  add(make_variant<ROLE_SPLIT_A, 512, 32, 16, 0, float2, 2>("a512p32w16q2_c64"));
+  add(make_variant<ROLE_SPLIT_A, 512, 32, 32, 0, float2, 2>("a512p32w32q2_c64"));
+  add(make_variant<ROLE_SPLIT_A, 1024, 16, 8, 0, float2, 2>("a1024p16w8q2_c64"));
+  add(make_variant<ROLE_SPLIT_A, 1024, 32, 8, 0, float2, 2>("a1024p32w8q2_c64"));
+  add(make_variant<ROLE_SPLIT_A, 1024, 32, 16, 0, float2, 2>("a1024p32w16q2_c64"));
   add(make_variant<ROLE_COL_TW, 2, 8, 8, 0, float2, 0>("t2p2w8_c64"));
   add(make_variant<ROLE_COL_TW, 2, 8, 16, 0, float2, 0>("t2p2w16_c64"));
   add(make_variant<ROLE_COL_TW, 2, 8, 32, 0, float2, 0>("t2p2w32_c64"));

@@ -50,7 +50,7 @@ def test_variant_registry(lib):
         d = capi.fft_variant_describe(i)
         assert name not in seen
         seen.add(name)
-        m = re.match(r"([ract])(\d+)p(\d+)w(\d+)(q?)(x?)_(c64|f16|bf16)$", name)
+        m = re.match(r"([ract])(\d+)p(\d+)w(\d+)(q2|q)?(x?)_(c64|f16|bf16)$", name)
         assert m, name
         assert int(m.group(2)) == d["L"] and int(m.group(3)) == d["P"] and int(m.group(4)) == d["W"]
         assert {"r": 0, "a": 1, "c": 2, "t": 3}[m.group(1)] == d["role"]

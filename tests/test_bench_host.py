@@ -12,7 +12,7 @@ if ROOT not in sys.path:
 
 import bench  # noqa: E402
 
-PIPE_A = "void mfft::k_pipe<1024, 32, 16, 1, 0, true, 0, HIP_vector_type<float, 2u> >(mfft::PassArgs)"
+PIPE_A = "void mfft::k_pipe<1024, 32, 16, 1, 0, true, 0, HIP_vector_type<float, 2u>, 1>(mfft::PassArgs)"
 STRIP_B = "void mfft::k_strip<1024, 32, 16, 1, 1, false, 1, HIP_vector_type<float, 2u> >(mfft::PassArgs)"
 COPY = "__amd_rocclr_copyBuffer"
 
@@ -42,10 +42,11 @@ def test_no_gpu_visible_is_an_error(capsys):
 
 
 @pytest.mark.parametrize("variant,sig", [
-    ("a1024p32w16q_c64", "k_pipe<1024, 32, 16, 1, 0, true, 0, HIP_vector_type<float, 2u> >"),
+    ("a1024p32w16q_c64", "k_pipe<1024, 32, 16, 1, 0, true, 0, HIP_vector_type<float, 2u>, 1>"),
+    ("a1024p32w16q2_c64", "k_pipe<1024, 32, 16, 1, 0, true, 0, HIP_vector_type<float, 2u>, 2>"),
     ("c1024p32w16x_c64", "k_strip<1024, 32, 16, 1, 1, false, 1, HIP_vector_type<float, 2u> >"),
     ("r256p16w16_f16", "k_strip<256, 16, 16, 0, 0, false, 0, __half2 >"),
-    ("a256p16w16q_bf16", "k_pipe<256, 16, 16, 1, 0, true, 0, mfft::c16bf >"),
+    ("a256p16w16q_bf16", "k_pipe<256, 16, 16, 1, 0, true, 0, mfft::c16bf, 1>"),
     ("not-a-variant", "not-a-variant"),
 ])
 def test_variant_kernel_signature(variant, sig):

@@ -136,6 +136,28 @@ def test_n2p20_batch16_forward_inverse(dev, which):
     assert e1.max() < 1e-6, float(e1.max())
 
 
+@pytest.mark.parametrize("n,batch,sched", [
+    # first pass with the loads of two tiles in flight: 1024 tiles on 256
+    # workgroups (4 each), 768 (3 each: the walk ends on the first register
+    # set), 320 (2 or 1 each), 64 (fewer tiles than workgroups)
+    (1 << 20, 16, "split=1024;a=a1024p32w16q2_c64;b=c1024p32w16x_c64"),
+    (1 << 20, 12, "split=1024;a=a1024p32w16q2_c64;b=c1024p32w16x_c64"),
+    (1 << 20, 5, "split=1024;xcd=10;a=a1024p32w16q2_c64;b=c1024p32w16x_c64"),
+    (1 << 20, 1, "split=1024;a=a1024p32w16q2_c64;b=c1024p32w16x_c64"),
+    # two step-row entries per lane (W x P = 2 x lanes)
+    (1 << 20, 12, "split=512;a=a512p32w32q2_c64"),
+    (1 << 16, 3, "split=256;a=a256p16w16q2_c64"),
+    (1 << 16, 64, "split=256;a=a256p16w16q2_c64"),
+    (1 << 18, 7, "split=512;a=a512p16w8q2_c64"),
+])
+@pytest.mark.parametrize("inverse", [False, True])
+def test_first_pass_two_tiles_in_flight(dev, n, batch, sched, inverse):
+    names = capi.fft_describe([n], batch, 1, capi.FFT_C64, sched)["names"]
+    assert names[0].endswith("q2_c64"), names
+    x = workloads.normal_batch(n, batch, seed=batch + n % 97)
+    check_1d(x, n, inverse, dev, schedule=sched)
+
+
 @pytest.mark.parametrize("which", ["built-in", "tuned"])
 def test_2d_4096x4096_speckle_image(dev, which):
     z = workloads.speckle_image(4096, 4096, seed=2)

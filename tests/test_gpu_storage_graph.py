@@ -45,6 +45,22 @@ def test_16bit_storage(dev, tname, shape):
 
 
 @pytest.mark.parametrize("tname", ["float16", "bfloat16"])
+@pytest.mark.parametrize("batch", [3, 16])
+def test_16bit_first_pass_two_tiles_in_flight(dev, tname, batch):
+    # 2^20 split 1024 x 1024, first pass with two tiles' loads in flight
+    tdt = getattr(torch, tname)
+    dt = "f16" if tname == "float16" else "bf16"
+    sched = f"split=1024;a=a1024p32w16q2_{dt};b=c1024p32w16qx_{dt}"
+    n = 1 << 20
+    x = workloads.normal_batch(n, batch, seed=batch + 11)
+    xq = quantised(x, tdt)
+    y = api.fft(to_gpu_16(x, dev, tdt), schedule=sched)
+    torch.cuda.synchronize()
+    err = rel_l2_rows(from_gpu_16(y).reshape(batch, -1), oracle.fft(xq).reshape(batch, -1), n)
+    assert err.max() <= TOL16[tname], float(err.max())
+
+
+@pytest.mark.parametrize("tname", ["float16", "bfloat16"])
 @pytest.mark.parametrize("shape", [(64, 512), (256, 32), (256, 16)])
 def test_16bit_three_pass_2d(dev, tname, shape):
     # columns as two sub-passes, forced by the schedule
