@@ -900,7 +900,7 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_many_2l(ManyArgs a) {
   constexpr int XN = many_lds_max<P, NT, MAXLG>();
   constexpr int TWN = many_tw_total<P, MAXLG>();
   __shared__ float2 lds[XN + TWN + 2 * NT];
-  __shared__ int s_idx[2], s_first[2], s_last;
+  __shared__ int s_idx[2], s_last;
   float2* xch = lds;
   float2* twl = lds + XN;
   float2* rowl = lds + XN + TWN;
@@ -912,14 +912,14 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_many_2l(ManyArgs a) {
   int* exits = heads + 8 + ph;
   constexpr int kNoClaim = 1 << 30;
 
-  // first two claims
-  if (tid == 0) {
-    s_first[0] = lo + atomicAdd(head, 1);
-    s_first[1] = lo + atomicAdd(head, 1);
-  }
-  __syncthreads();  // claims visible
-  int c = min(s_first[0], hi);
-  int n = min(s_first[1], hi);
+  // The first two items are fixed: g and G + g for workgroup g of G.  Every
+  // workgroup starts at once, and 2G claims on the one queue head at the
+  // start would be served one after another (several microseconds for the
+  // last in line); later claims come spread over the launch.  Claim k
+  // (0-based) then names item 2G + k.
+  const int G = (int)gridDim.x;
+  int c = min(lo + (int)blockIdx.x, hi);
+  int n = min(lo + G + (int)blockIdx.x, hi);
   ManyItemX dc = xitem(a, c, hi);
   ManyItemX dn = xitem(a, n, hi);
   int64_t base_c = 0, base_n = 0;
@@ -969,7 +969,7 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_many_2l(ManyArgs a) {
       tw_base = cmul(pre.hin, pre.lon);
     }
     // the index of the item after n
-    if (tid == 0) s_idx[par] = min(lo + claim, hi);
+    if (tid == 0) s_idx[par] = min(lo + 2 * G + claim, hi);
     lds_barrier();  // also: step rows visible
     const int n2 = s_idx[par];
     par ^= 1;

@@ -237,6 +237,41 @@ def test_two_launch_split(schedule):
         assert np.all(first_tiles[lg == 12] > 0)
 
 
+def simulate_two_launch(n_items, workers, rng):
+    """One launch of the two-launch kernel: worker g starts with items g and
+    workers + g, then claim k (in the order the claims reach the queue head)
+    names item 2 * workers + k; an index past the end stops the worker.
+    Returns how many times each item ran."""
+    ran = np.zeros(n_items, int)
+    head = 0
+    cur = [g if g < n_items else None for g in range(workers)]
+    nxt = [workers + g if workers + g < n_items else None for g in range(workers)]
+    live = [g for g in range(workers) if cur[g] is not None]
+    while live:
+        g = live[int(rng.integers(len(live)))]
+        ran[cur[g]] += 1
+        cur[g] = nxt[g]
+        nxt[g] = None
+        if cur[g] is not None:
+            k = head
+            head += 1
+            if 2 * workers + k < n_items:
+                nxt[g] = 2 * workers + k
+        else:
+            live.remove(g)
+    return ran
+
+
+@pytest.mark.parametrize("n_items,workers", [(846, 256), (854, 256), (1, 256), (255, 256), (256, 256),
+                                             (511, 256), (512, 256), (513, 256), (100, 1), (100, 7)])
+def test_two_launch_static_first_items(n_items, workers):
+    # every item of a launch runs exactly once under the fixed first two
+    # items and the dynamic claims after them, whatever order workers finish in
+    for seed in range(3):
+        ran = simulate_two_launch(n_items, workers, np.random.default_rng(seed))
+        assert np.all(ran == 1)
+
+
 def test_per_length_schedule_items():
     sizes = [1 << 14, 1 << 9, 1 << 16]
     _, fl, ft = capi.fft_describe_many(sizes, capi.FFT_C64, "n1.14=5;pass.9=2;n1.16=12")
