@@ -108,6 +108,15 @@ int fft_plan(const int64_t *n, int64_t batch, int dims, int dtype, int direction
  *             | 'col3=' 0|1           (2-D: columns as two sub-passes of sqrt(rows)
  *                                       points; rows a power of 4, at least 2 columns)
  *             | 'colt=' variant       (the first of those sub-passes)
+ *             | 'rowcol=' 0|2|4       (2-D, complex64: the row pass also takes the
+ *                                       first radix-r step of the columns (R =
+ *                                       r*M, eq. 5): a tile holds rows n1 + M*j,
+ *                                       j < r, and writes rows r*n1 + k2; then
+ *                                       M-point columns over rows r*n1 + k2,
+ *                                       in place, whose tiles can be r times
+ *                                       wider.  'row=' then names a fused
+ *                                       variant ('f'), 'col=' an M-point column
+ *                                       variant.  In place needs a workspace.)
  *             | 'method=' lds|levels  (1-D only.  'levels' is the method the
  *                                       paper replaces (Sec. 2.2, Fig. 2), kept
  *                                       for comparison: one radix-2 kernel per
@@ -320,8 +329,9 @@ int fft_last_hip_error(void);
  * fft_variant_describe(i, ...) its sub-transform length L, points per lane
  * P, transforms per workgroup W, workgroup size and role (0 contiguous rows,
  * 1 first pass of a split, 2 strided columns, 3 strided columns with a
- * twiddle).  Names read <role><L>p<P>w<W>[q|q2][x]_<dtype>: role r, a, c, t
- * as above; q a persistent kernel (one workgroup per CU walking the tiles)
+ * twiddle, 4 rows fused with a radix-W column step).  Names read
+ * <role><L>p<P>w<W>[q|q2][x]_<dtype>: role r, a, c, t, f as above; q a
+ * persistent kernel (one workgroup per CU walking the tiles)
  * with the next tile's loads in flight while one is computed, q2 with the
  * next two; x the exchange through LDS in two rounds (real, then
  * imaginary parts), which halves its LDS footprint.

@@ -35,7 +35,7 @@ ARCH = "gfx950"
 _lock = threading.Lock()
 _cache = None
 
-ROLE_ROW, ROLE_A, ROLE_COL, ROLE_COL_TW = 0, 1, 2, 3
+ROLE_ROW, ROLE_A, ROLE_COL, ROLE_COL_TW, ROLE_ROWCOL = 0, 1, 2, 3, 4
 
 
 def _load_cache() -> dict:
@@ -156,8 +156,8 @@ def tune_plan(shape, batch, dtype=capi.FFT_C64, reps=10, verbose=False):
     bufs = _Buffers(n * batch, esize, torch)
     var = [v for v in _variants() if v["dtype"] == dtype]
 
-    def names(role, L):
-        return [v["name"] for v in var if v["role"] == role and v["L"] == L]
+    def names(role, L, W=None):
+        return [v["name"] for v in var if v["role"] == role and v["L"] == L and (W is None or v["W"] == W)]
 
     results = []
 
@@ -189,6 +189,12 @@ def tune_plan(shape, batch, dtype=capi.FFT_C64, reps=10, verbose=False):
             sq = 1 << (lg_r // 2)
             keys3 = [("colt", ROLE_COL_TW, sq), ("col", ROLE_COL, sq), ("row", ROLE_ROW, shape[1])]
             starts = [{"col3": 0}, ({"col3": 1}, keys3)]
+        for r in (4, 2):
+            # rows fused with the first radix-r step of the columns, then
+            # columns of R/r points
+            if shape[0] >= 2 * r and run(f"rowcol={r}") is not None:
+                keysf = [("row", ROLE_ROWCOL, shape[1]), ("col", ROLE_COL, shape[0] // r)]
+                starts.append(({"rowcol": r}, keysf))
     elif info["passes"] == 1 and shape[0] > 1:
         keys.append(("single", ROLE_ROW, shape[0]))
         splits = [None]
@@ -229,7 +235,8 @@ def tune_plan(shape, batch, dtype=capi.FFT_C64, reps=10, verbose=False):
         for _ in range(2):
             for key, role, L in keys:
                 best = None
-                for nm in names(role, L):
+                # a fused row pass must match the plan's column radix
+                for nm in names(role, L, cur.get("rowcol") if role == ROLE_ROWCOL else None):
                     trial = dict(cur)
                     trial[key] = nm
                     s = ";".join(f"{k}={v}" for k, v in trial.items())

@@ -254,6 +254,16 @@ __device__ __forceinline__ int64_t tile_of(int64_t b, int64_t n, int remap) {
   return (b & 7) * (n >> 3) + (b >> 3);
 }
 
+// Wait until at most N vector memory operations of this wave are
+// outstanding.
+template <int N>
+__device__ __forceinline__ void vm_wait() {
+  // s_waitcnt: vmcnt in bits [3:0] and [15:14], expcnt [6:4] = 7 and
+  // lgkmcnt [11:8] = 15 left at their maxima (not waited for)
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
 // Workgroup barrier that orders LDS accesses only (fences scoped to the
 // "local" address space): global loads issued before it stay in flight, which
 // is what lets the persistent kernel prefetch the next tile across the
@@ -676,9 +686,15 @@ k_pipe(PassArgs a) {
   // segment is narrower than a line, are in flight on one L2 together
   const int64_t G = gridDim.x;
   int64_t tile = tile_of(blockIdx.x, G, a.xcd_remap);
+  // The prologue's prefetch is drained before the walk starts, so that the
+  // top of the loop sees the same memory state from the prologue as from
+  // its back edge (the previous tile's stores in flight, its prefetch
+  // done); otherwise the compiler's wait at the top, which must hold for
+  // both paths, waits for those stores as well.
   if constexpr (DEPTH == 1) {
     Pre pa;
     if (tile < a.total_tiles) prefetch(pa, tile);
+    vm_wait<0>();
     lds_barrier();  // stage twiddles visible
     for (; tile < a.total_tiles; tile += G) body(pa, tile, tile + G);
   } else {
@@ -687,6 +703,7 @@ k_pipe(PassArgs a) {
     Pre pa, pb;
     if (tile < a.total_tiles) prefetch(pa, tile);
     if (tile + G < a.total_tiles) prefetch(pb, tile + G);
+    vm_wait<0>();
     lds_barrier();  // stage twiddles visible
     for (; tile < a.total_tiles; tile += 2 * G) {
       body(pa, tile, tile + 2 * G);

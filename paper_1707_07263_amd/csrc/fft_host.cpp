@@ -55,6 +55,7 @@ const std::vector<Variant>& variants() {
     add_variants_c64_col(add_one);
     add_variants_c64_col2(add_one);
     add_variants_c64_pipe(add_one);
+    add_variants_c64_rowcol(add_one);
     add_variants_c16(add_one);
   });
   return *g_variants;
@@ -115,6 +116,8 @@ struct PassSpec {
   bool first = false, last = false;
   int64_t tw_N = 0;            // inter-pass twiddle modulus (0: none)
   int64_t tw_rows = 0;         // rows of its step table
+  int64_t colr_N = 0;          // fused row pass: its column twiddles W_R^e, e < colr_N (0: none)
+  int64_t scale_len = 0;       // transform length this pass accounts for (0: the variant's L)
   std::vector<int32_t> line_map;  // row pass of the three-pass 2-D plan
   // launched once per transform of the batch, pointers advanced by the
   // transform's length (the last pass of the three-pass 1-D plan)
@@ -149,6 +152,7 @@ struct Overrides {
   bool mfma = false;    // method=mfma: matrix-core radix-16 stages (N = 256)
   int xlane = 0;        // method=xlane (1) | xlane_bperm (2): cross-lane exchange (N = 256)
   int blk = 0;  // 2-D: intermediate in column blocks of blk columns (0: natural order)
+  int rowcol = 0;  // 2-D: row pass fused with a radix-rowcol column step (0: off)
   std::string a, b, row, col, single, colt;
 };
 
@@ -192,6 +196,11 @@ int parse_schedule(const char* s, Overrides* o) {
       else if (val == "8") o->blk = 8;
       else if (val == "16") o->blk = 16;
       else if (val == "32") o->blk = 32;
+      else return FFT_ERR_INVALID_ARGUMENT;
+    } else if (key == "rowcol") {
+      if (val == "0") o->rowcol = 0;
+      else if (val == "2") o->rowcol = 2;
+      else if (val == "4") o->rowcol = 4;
       else return FFT_ERR_INVALID_ARGUMENT;
     } else if (key == "method") {
       if (val != "lds" && val != "levels" && val != "mfma" && val != "xlane" && val != "xlane_bperm")
@@ -391,6 +400,7 @@ int build_schedule_inner(const int64_t* n, int64_t batch, int dims, int dtype, c
   Schedule S;
   if (dims == 1) {
     const int64_t N = n[0];
+    if (ov.rowcol) return FFT_ERR_INVALID_ARGUMENT;  // 2-D only
     if (!pow2(N) || ilog2_64(N) > FFT_MAX_LOG2_1D) return FFT_ERR_UNSUPPORTED_SIZE;
     if (batch > ((int64_t)1 << 40) / N) return FFT_ERR_UNSUPPORTED_SIZE;
     S.points = N * batch;
@@ -487,6 +497,62 @@ int build_schedule_inner(const int64_t* n, int64_t batch, int dims, int dtype, c
     if (batch > ((int64_t)1 << 40) / (R * C)) return FFT_ERR_UNSUPPORTED_SIZE;
     S.points = R * C * batch;
     const int lgR = ilog2_64(R);
+    if (ov.rowcol) {
+      // rows fused with the first radix-r step of the columns (R = r*M),
+      // then M-point columns over rows r*n1 + k2 for each k2, in place
+      const int r = ov.rowcol;
+      if (ov.col3 == 1 || ov.blk || R < 2 * r || C < 2) return FFT_ERR_INVALID_ARGUMENT;
+      const int64_t M = R / r;
+      PassSpec f, cl;
+      if (!ov.row.empty()) {
+        f.v = find_by_name(ov.row);
+        if (!f.v || f.v->role != ROLE_ROWCOL || f.v->L != C || f.v->dtype != dtype) return FFT_ERR_INVALID_ARGUMENT;
+      } else {
+        // the first registered fused variant of this row length and radix
+        for (const Variant& v : variants())
+          if (v.role == ROLE_ROWCOL && v.L == C && v.dtype == dtype && v.W == r) {
+            f.v = &v;
+            break;
+          }
+        if (!f.v) return FFT_ERR_UNSUPPORTED_SIZE;
+      }
+      if (f.v->W != r) return FFT_ERR_INVALID_ARGUMENT;
+      int rc;
+      rc = choose(ov.col, ROLE_COL, (int)M, dtype, 16, C, &cl.v);
+      if (rc) return rc;
+      if (M * batch > INT32_MAX) return FFT_ERR_UNSUPPORTED_SIZE;
+      PassArgs& a = f.args;
+      a.in_batch = a.out_batch = R * C;
+      a.in_line = a.out_line = C;
+      a.in_elem = a.out_elem = 1;
+      a.lines = (int32_t)R;
+      a.tiles_per_batch = (int32_t)M;
+      a.total_tiles = M * batch;
+      a.tw_shift = ilog2_64(M);
+      f.colr_N = R;
+      f.scale_len = r * C;
+      f.src = SEL_IN;
+      f.dst = SEL_OUT;
+      f.first = true;
+      // columns: line c, points k1 at stride r*C; block k2 starts at row k2
+      // (one image per launch when batched)
+      PassArgs& b = cl.args;
+      b.in_line = b.out_line = 1;
+      b.in_elem = b.out_elem = r * C;
+      b.in_batch = b.out_batch = C;
+      b.lines = (int32_t)C;
+      b.tiles_per_batch = (int32_t)((C + cl.v->W - 1) / cl.v->W);
+      b.total_tiles = (int64_t)b.tiles_per_batch * r;
+      cl.per_transform = true;
+      cl.src = SEL_OUT;
+      cl.dst = SEL_OUT;
+      cl.last = true;
+      S.inplace_needs_ws = true;
+      S.passes.push_back(f);
+      S.passes.push_back(cl);
+      *out = S;
+      return FFT_OK;
+    }
     if (ov.blk) {
       // the intermediate in column blocks (row pass -> workspace, column
       // pass -> out): every column tile then reads one contiguous block
@@ -972,6 +1038,7 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
       hi_off[i] = tb.add(M >> sh, 0, M, (int64_t)1 << sh);
       step_off[i] = tb.add(ps.tw_rows * ps.v->P, ps.v->P, M, T);
     }
+    if (ps.colr_N) lo_off[i] = tb.add(ps.colr_N, 0, ps.colr_N, 1);  // W_R^e, e < R
   }
   if (S.levels) tb.add(n[0] / 2, 0, n[0], 1);  // W_N^m, m < N/2
   if (S.mfma || S.xlane) tb.add(256, 0, 256, 1);          // W_256^m, m < 256
@@ -1023,6 +1090,7 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
       ps.args.tw_hi = p->d_tables + hi_off[i];
       ps.args.tw_step = p->d_tables + step_off[i];
     }
+    if (ps.colr_N) ps.args.tw_lo = p->d_tables + lo_off[i];
     if (!ps.line_map.empty()) {
       const size_t bytes = ps.line_map.size() * sizeof(int32_t);
       int32_t* d = nullptr;
@@ -1222,7 +1290,7 @@ int exec_impl(fft_plan_t p, const void* in, void* out, void* stream, void* ws_ov
       // powers of two, so the result is unchanged, and 16-bit intermediates
       // stay in range); a scale set by the caller is applied by the last pass
       a.scale = p->scale_user ? (ps.last ? (float)p->scale : 1.0f)
-                              : (inv ? 1.0f / (float)ps.v->L : 1.0f);
+                              : (inv ? 1.0f / (float)(ps.scale_len ? ps.scale_len : ps.v->L) : 1.0f);
       a.conj_in = (inv && ps.first) ? 1 : 0;
       a.conj_out = (inv && ps.last) ? 1 : 0;
       if (ps.per_transform && p->batch > 1) {

@@ -144,6 +144,22 @@ def c16_set():
     return list(dict.fromkeys(out))
 
 
+def rowcol_set():
+    """2-D row passes fused with a radix-4 column step (k_rowcol): row
+    lengths 256 .. 4096, four rows per tile; the two-round exchange where
+    the one-round one would not fit in LDS beside the stage table."""
+    out = []
+    for lg in range(8, 13):
+        L = 1 << lg
+        P = 16 if L <= 512 else 32
+        ex = 1 if L >= 4096 else 0
+        out.append((L, P, 4, ex))
+    # 4096-point rows: 1024 lanes of 16 points (more waves per CU), and a
+    # radix-2 column step (two rows per tile: half the LDS)
+    out += [(4096, 16, 4, 1), (4096, 32, 2, 1), (2048, 32, 2, 0)]
+    return out
+
+
 def name(role, L, P, W, ex, dt, persist=0):
     # q: persistent with the next tile in flight; q2: the next two tiles
     q = {0: "", 1: "q", 2: "q2"}[persist]
@@ -205,7 +221,10 @@ def emit(fname, func, items):
         lines.append(f'  add(make_variant<{ROLE[role]}, {L}, {P}, {W}, {ex}, {DT[dt]}, {persist}>'
                      f'("{name(role, L, P, W, ex, dt, persist)}"));')
     lines += ["}", "", "}  // namespace mfft", ""]
-    text = "\n".join(lines)
+    emit_text(fname, "\n".join(lines))
+
+
+def emit_text(fname, text):
     path = os.path.join(HERE, fname)
     if not os.path.exists(path) or open(path).read() != text:
         if _CHECK is not None:
@@ -243,6 +262,13 @@ def main():
     pipe += [v + ("c64", 2) for v in pipe_set() if v[0] == "a"]
     emit("variants_c64_pipe.hip", "add_variants_c64_pipe",
          pipe + [("t",) + v + ("c64",) for v in coltw_set()])
+    lines = ['#include "variants.hpp"', "", "namespace mfft {", "",
+             "void add_variants_c64_rowcol(void (*add)(const Variant&)) {"]
+    for L, P, W, ex in rowcol_set():
+        lines.append(f'  add(make_rowcol_variant<{L}, {P}, {W}, {ex}, float2>'
+                     f'("{name("f", L, P, W, ex, "c64", 1)}"));')
+    lines += ["}", "", "}  // namespace mfft", ""]
+    emit_text("variants_c64_rowcol.hip", "\n".join(lines))
 
 
 if __name__ == "__main__":

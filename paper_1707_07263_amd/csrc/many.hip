@@ -661,14 +661,6 @@ __global__ void __launch_bounds__(NT, 1) k_many_pipe(ManyArgs a) {
 // single-launch kernel above to a third of peak.)
 // ---------------------------------------------------------------------------
 
-// Wait until at most N vector-memory operations of this wave are in flight.
-template <int N>
-__device__ __forceinline__ void vm_wait() {
-  // s_waitcnt: vmcnt in bits [3:0] and [15:14], expcnt [6:4] = 7 and
-  // lgkmcnt [11:8] = 15 left at their maxima (not waited for)
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
 
 // The per-lane loads of an item, issued ahead of its butterflies.
 template <int P>

@@ -8,10 +8,12 @@
 #include <stdint.h>
 
 #include "fft_device.hpp"
+#include "rowcol.hpp"
 
 namespace mfft {
 
-enum Role { ROLE_ROW = 0, ROLE_SPLIT_A = 1, ROLE_COL = 2, ROLE_COL_TW = 3 };
+// ROLE_ROWCOL: 2-D row pass fused with a radix-W column step (k_rowcol)
+enum Role { ROLE_ROW = 0, ROLE_SPLIT_A = 1, ROLE_COL = 2, ROLE_COL_TW = 3, ROLE_ROWCOL = 4 };
 enum Dtype { DT_C64 = 0, DT_C16F = 1, DT_C16BF = 2 };
 
 // start/stop: events (or null) that take the kernel's own start and end
@@ -90,6 +92,44 @@ Variant make_variant(const char* name) {
   return v;
 }
 
+template <int L, int P, int W, int EX, typename TS>
+hipError_t launch_rowcol(const PassArgs& a, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+  constexpr int NT = W * Sched<L, P>::T;
+  const unsigned grid = (unsigned)(a.grid > 0 ? a.grid : a.total_tiles);
+  hipExtLaunchKernelGGL((k_rowcol<L, P, W, EX, TS>), dim3(grid), dim3(NT), 0, s, start, stop, 0, a);
+  return hipGetLastError();
+}
+
+template <int L, int P, int W, int EX, typename TS>
+int blocks_rowcol() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rowcol<L, P, W, EX, TS>, W * Sched<L, P>::T, 0) !=
+      hipSuccess)
+    return 0;
+  return n;
+}
+
+// A fused row pass: L = row length, W = rows per tile = radix of its
+// column step, persistent.
+template <int L, int P, int W, int EX, typename TS>
+Variant make_rowcol_variant(const char* name) {
+  Variant v;
+  v.name = name;
+  v.L = L;
+  v.P = Sched<L, P>::PP;
+  v.W = W;
+  v.threads = W * Sched<L, P>::T;
+  v.role = ROLE_ROWCOL;
+  v.dtype = DtOf<TS>::v;
+  v.tw_entries = Sched<L, P>::TW;
+  v.ex = EX;
+  v.persistent = 1;
+  v.lds_bytes = rowcol_lds_entries<L, P, W, EX>() * 8;
+  v.launch = &launch_rowcol<L, P, W, EX, TS>;
+  v.blocks_per_cu = &blocks_rowcol<L, P, W, EX, TS>;
+  return v;
+}
+
 // Each instantiation file appends its variants.
 void add_variants_c64_row(void (*add)(const Variant&));
 void add_variants_c64_a(void (*add)(const Variant&));
@@ -97,6 +137,7 @@ void add_variants_c64_col(void (*add)(const Variant&));
 void add_variants_c64_col2(void (*add)(const Variant&));
 void add_variants_c64_pipe(void (*add)(const Variant&));
 void add_variants_c16(void (*add)(const Variant&));
+void add_variants_c64_rowcol(void (*add)(const Variant&));
 
 // trivial length-1 / copy-scale kernel
 hipError_t launch_scale_copy(int dtype, const void* in, void* out, int64_t n, float scale,

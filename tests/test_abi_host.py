@@ -50,10 +50,10 @@ def test_variant_registry(lib):
         d = capi.fft_variant_describe(i)
         assert name not in seen
         seen.add(name)
-        m = re.match(r"([ract])(\d+)p(\d+)w(\d+)(q2|q)?(x?)_(c64|f16|bf16)$", name)
+        m = re.match(r"([ractf])(\d+)p(\d+)w(\d+)(q2|q)?(x?)_(c64|f16|bf16)$", name)
         assert m, name
         assert int(m.group(2)) == d["L"] and int(m.group(3)) == d["P"] and int(m.group(4)) == d["W"]
-        assert {"r": 0, "a": 1, "c": 2, "t": 3}[m.group(1)] == d["role"]
+        assert {"r": 0, "a": 1, "c": 2, "t": 3, "f": 4}[m.group(1)] == d["role"]
         assert {"c64": 0, "f16": 1, "bf16": 2}[m.group(7)] == d["dtype"]
         assert d["threads"] == d["W"] * d["L"] // d["P"] and d["threads"] <= 1024
     assert capi.fft_variant_name(n) is None
@@ -200,6 +200,24 @@ def test_describe_levels_method(lib):
         with pytest.raises(capi.FFTError) as ei:
             capi.fft_describe(n, 1, dims, capi.FFT_C64, bad)
         assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT
+
+
+def test_describe_rows_fused_with_column_step(lib):
+    # rowcol=4: the row pass takes the first radix-4 step of the columns,
+    # leaving columns of R/4 points
+    for (r, c), col_len in (((4096, 4096), 1024), ((64, 256), 16), ((8, 1024), 2)):
+        d = capi.fft_describe([r, c], 2, 2, capi.FFT_C64, "rowcol=4")
+        assert d["passes"] == 2 and re.match(rf"f{c}p\d+w4qx?_c64$", d["names"][0]), d
+        assert re.match(rf"c{col_len}p\d+w\d+", d["names"][1]), d
+    d = capi.fft_describe([4096, 4096], 1, 2, capi.FFT_C64, "rowcol=2")
+    assert d["names"][0] == "f4096p32w2qx_c64" and d["names"][1].startswith("c2048")
+    for bad in ("rowcol=8", "rowcol=4;col3=1", "rowcol=4;blk=8", "rowcol=x", "rowcol=2;row=f4096p16w4qx_c64"):
+        with pytest.raises(capi.FFTError):
+            capi.fft_describe([4096, 4096], 1, 2, capi.FFT_C64, bad)
+    # no fused variant for this row length, too few rows, or 1-D
+    for shape, dims in (([64, 128], 2), ([4, 1024], 2), ([1 << 20], 1)):
+        with pytest.raises(capi.FFTError):
+            capi.fft_describe(shape, 1, dims, capi.FFT_C64, "rowcol=4")
 
 
 def test_describe_dft256_experiments(lib):
