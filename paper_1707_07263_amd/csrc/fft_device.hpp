@@ -274,6 +274,11 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Entries of the two factor tables of W_L (TWP 2): 2^LA + 2^(log2 L - LA).
+__host__ __device__ constexpr int tw_split_entries(int L) {
+  return (1 << ((ilog2(L) + 1) / 2)) + (1 << (ilog2(L) - (ilog2(L) + 1) / 2));
+}
+
 // Stage twiddles staged in LDS: the same entries as the global table, with
 // each k-row of R factors padded to R + 2 so that lanes reading different
 // rows with 16-byte loads start on different banks.
@@ -376,7 +381,18 @@ struct Stage {
       float2 x[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) x[r] = v[b + r * NB];
-      if constexpr (s > 0) {
+      if constexpr (s > 0 && TWP == 2) {
+        // TWP 2: W_{NS*R}^{k r} = W_L^e, e = k r L/(NS R), from two factor
+        // tables in LDS, twt[i] = W_L^i (i < 2^LA) and
+        // twt[2^LA + i] = W_L^{i 2^LA}: a few hundred bytes instead of the
+        // stage table
+        constexpr int LG = ilog2(L), LA = (LG + 1) / 2, SC = L / (NS * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const int e = k * r * SC;
+          x[r] = cmul(x[r], cmul(twt[e & ((1 << LA) - 1)], twt[(1 << LA) + (e >> LA)]));
+        }
+      } else if constexpr (s > 0) {
         // TWP 0: global table; TWP 1: LDS copy with padded rows
         const float2* tw = TWP == 0 ? twt + S::off(s) + k * R
                                     : twt + TwLds<L, P>::off(s) + k * TwLds<L, P>::rp(s);

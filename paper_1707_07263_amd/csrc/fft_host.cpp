@@ -1027,7 +1027,14 @@ int fft_plan_ex(const int64_t* n, int64_t batch, int dims, int dtype, int direct
   for (size_t i = 0; i < S.passes.size(); ++i) {
     const PassSpec& ps = S.passes[i];
     if (!ps.v) continue;
-    stage_off[i] = tb.add_stage_table(ps.v->L, ps.v->P);
+    if (ps.v->tw_split) {
+      // the two factor tables of W_L: W_L^i (i < 2^a), W_L^{i 2^a}
+      const int lg = ilog2_64(ps.v->L), la = (lg + 1) / 2;
+      stage_off[i] = tb.add((int64_t)1 << la, 0, ps.v->L, 1);
+      tb.add((int64_t)1 << (lg - la), 0, ps.v->L, (int64_t)1 << la);
+    } else {
+      stage_off[i] = tb.add_stage_table(ps.v->L, ps.v->P);
+    }
     if (ps.tw_N) {
       // W_M^{row*k} with k = t + q*T: a per-lane base W_M^{row*t} (lo/hi
       // factors) times a per-row step W_M^{row*q*T} (table [rows][P])

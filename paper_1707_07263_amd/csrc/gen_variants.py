@@ -157,7 +157,12 @@ def rowcol_set():
     # 4096-point rows: 1024 lanes of 16 points (more waves per CU), and a
     # radix-2 column step (two rows per tile: half the LDS)
     out += [(4096, 16, 4, 1), (4096, 32, 2, 1), (2048, 32, 2, 0)]
-    return out
+    return [v + (1,) for v in out] + SPLIT_TW_ROWCOL
+
+
+# fused row passes whose stage twiddles come from two factor tables of W_L
+# (TWP 2): the LDS then holds a one-round exchange of four 4096-point rows
+SPLIT_TW_ROWCOL = [(4096, 16, 4, 0, 2), (4096, 32, 4, 0, 2)]
 
 
 def name(role, L, P, W, ex, dt, persist=0):
@@ -264,8 +269,8 @@ def main():
          pipe + [("t",) + v + ("c64",) for v in coltw_set()])
     lines = ['#include "variants.hpp"', "", "namespace mfft {", "",
              "void add_variants_c64_rowcol(void (*add)(const Variant&)) {"]
-    for L, P, W, ex in rowcol_set():
-        lines.append(f'  add(make_rowcol_variant<{L}, {P}, {W}, {ex}, float2>'
+    for L, P, W, ex, twp in rowcol_set():
+        lines.append(f'  add(make_rowcol_variant<{L}, {P}, {W}, {ex}, {twp}, float2>'
                      f'("{name("f", L, P, W, ex, "c64", 1)}"));')
     lines += ["}", "", "}  // namespace mfft", ""]
     emit_text("variants_c64_rowcol.hip", "\n".join(lines))

@@ -23,17 +23,21 @@
 
 namespace mfft {
 
-template <int L, int P, int W, int EX>
+// TWP 1: the stage twiddles in LDS; TWP 2: built from two factor tables of
+// W_L, which leaves the LDS to a one-round exchange of the four rows
+template <int L, int P, int W, int EX, int TWP>
 __host__ __device__ constexpr int rowcol_lds_entries() {
-  return (EX == 0 ? W * LdsLayout<L>::LS : (W * LdsLayout<L>::LS + 1) / 2) + TwLds<L, P>::SIZE;
+  return (EX == 0 ? W * LdsLayout<L>::LS : (W * LdsLayout<L>::LS + 1) / 2) +
+         (TWP == 2 ? tw_split_entries(L) : TwLds<L, P>::SIZE);
 }
 
 // PassArgs as used here: lines = R rows per image, tiles_per_batch = M =
 // R / W (a power of two, tw_shift = log2 M), in_line = out_line = C,
 // in_elem = out_elem = 1, in_batch = out_batch = R * C, tw = the row length's
-// stage table, tw_lo = W_R^e for e < R.  Persistent: workgroup g walks tiles
+// stage table (TWP 1) or the factor tables of W_L (TWP 2), tw_lo = W_R^e
+// for e < R.  Persistent: workgroup g walks tiles
 // g, g + G, ... with the next tile's loads in flight.
-template <int L, int P, int W, int EX, typename TS>
+template <int L, int P, int W, int EX, int TWP, typename TS>
 __global__ void __launch_bounds__((W * Sched<L, P>::T), 1) k_rowcol(PassArgs a) {
   using S = Sched<L, P>;
   using LY = LdsLayout<L>;
@@ -44,12 +48,16 @@ __global__ void __launch_bounds__((W * Sched<L, P>::T), 1) k_rowcol(PassArgs a) 
   static_assert(W == 2 || W == 4, "radix of the fused column step");
   static_assert(CPL * W == PP && CPL * NT == L, "a lane takes CPL columns of all W rows");
   constexpr int XN = EX == 0 ? W * LY::LS : (W * LY::LS + 1) / 2;
-  __shared__ float2 lds[rowcol_lds_entries<L, P, W, EX>()];
+  __shared__ float2 lds[rowcol_lds_entries<L, P, W, EX, TWP>()];
   float2* xch = lds;
   float2* twl = lds + XN;
 
   int tid = threadIdx.x;
-  TwLds<L, P>::copy(twl, a.tw, tid, NT);
+  if constexpr (TWP == 2) {
+    for (int i = tid; i < tw_split_entries(L); i += NT) twl[i] = a.tw[i];
+  } else {
+    TwLds<L, P>::copy(twl, a.tw, tid, NT);
+  }
   const int lgM = a.tw_shift;
   const int64_t M = (int64_t)1 << lgM;
   const uint32_t sgn_in = a.conj_in ? 0x80000000u : 0u;
@@ -106,7 +114,7 @@ __global__ void __launch_bounds__((W * Sched<L, P>::T), 1) k_rowcol(PassArgs a) 
 
     // the W row transforms (contiguous rows in and out: point-fastest lanes)
     int m = tid / T, t = tid % T;
-    run_stages<L, P, W, EX, 1>(v, xch, m, t, m, t, false, twl);
+    run_stages<L, P, W, EX, TWP>(v, xch, m, t, m, t, false, twl);
 
     // column step: lane tid takes columns c = tid + i*NT of every row j,
     // v[j*CPL + i] <- row j, column c (the exchange buffer is free: the

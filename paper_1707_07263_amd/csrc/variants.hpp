@@ -26,6 +26,7 @@ struct Variant {
   int lds_bytes;
   int tw_entries;  // stage-table entries for this (L, P)
   int ex;          // LDS exchange: 0 = (re, im) pairs, 1 = real then imaginary
+  int tw_split = 0;  // stage twiddles from the two factor tables of W_L (k_rowcol TWP 2)
   int persistent;  // k_pipe (grid = resident workgroups, tiles walked in a loop) with
                    // 1 or 2 tiles' loads in flight; 0: k_strip
   LaunchFn launch;
@@ -92,18 +93,18 @@ Variant make_variant(const char* name) {
   return v;
 }
 
-template <int L, int P, int W, int EX, typename TS>
+template <int L, int P, int W, int EX, int TWP, typename TS>
 hipError_t launch_rowcol(const PassArgs& a, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   constexpr int NT = W * Sched<L, P>::T;
   const unsigned grid = (unsigned)(a.grid > 0 ? a.grid : a.total_tiles);
-  hipExtLaunchKernelGGL((k_rowcol<L, P, W, EX, TS>), dim3(grid), dim3(NT), 0, s, start, stop, 0, a);
+  hipExtLaunchKernelGGL((k_rowcol<L, P, W, EX, TWP, TS>), dim3(grid), dim3(NT), 0, s, start, stop, 0, a);
   return hipGetLastError();
 }
 
-template <int L, int P, int W, int EX, typename TS>
+template <int L, int P, int W, int EX, int TWP, typename TS>
 int blocks_rowcol() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rowcol<L, P, W, EX, TS>, W * Sched<L, P>::T, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rowcol<L, P, W, EX, TWP, TS>, W * Sched<L, P>::T, 0) !=
       hipSuccess)
     return 0;
   return n;
@@ -111,7 +112,7 @@ int blocks_rowcol() {
 
 // A fused row pass: L = row length, W = rows per tile = radix of its
 // column step, persistent.
-template <int L, int P, int W, int EX, typename TS>
+template <int L, int P, int W, int EX, int TWP, typename TS>
 Variant make_rowcol_variant(const char* name) {
   Variant v;
   v.name = name;
@@ -123,10 +124,11 @@ Variant make_rowcol_variant(const char* name) {
   v.dtype = DtOf<TS>::v;
   v.tw_entries = Sched<L, P>::TW;
   v.ex = EX;
+  v.tw_split = TWP == 2;
   v.persistent = 1;
-  v.lds_bytes = rowcol_lds_entries<L, P, W, EX>() * 8;
-  v.launch = &launch_rowcol<L, P, W, EX, TS>;
-  v.blocks_per_cu = &blocks_rowcol<L, P, W, EX, TS>;
+  v.lds_bytes = rowcol_lds_entries<L, P, W, EX, TWP>() * 8;
+  v.launch = &launch_rowcol<L, P, W, EX, TWP, TS>;
+  v.blocks_per_cu = &blocks_rowcol<L, P, W, EX, TWP, TS>;
   return v;
 }
 

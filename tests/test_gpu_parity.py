@@ -337,6 +337,17 @@ def test_persistent_variants(dev, name):
     i = [c.fft_variant_name(k) for k in range(c.fft_variant_count())].index(name)
     d = c.fft_variant_describe(i)
     L = d["L"]
+    if d["role"] == 4:      # 2-D rows fused with a radix-W column step
+        r, W = 1024, d["W"]
+        batch = 3          # r / W * 3 tiles: more than resident workgroups
+        sched = f"rowcol={W};row={name}"
+        x = workloads.normal_batch(r * L, batch, seed=L + W).reshape(batch, r, L)
+        for inv, sc in ((False, sched), (True, sched + ";xcd=1")):
+            got = run_c64(x, [r, L], inverse=inv, schedule=sc, dev=dev)
+            ref = oracle.fft2(x.astype(np.complex64), inverse=inv)
+            err = rel_l2_rows(got.reshape(batch, -1), ref.reshape(batch, -1), r * L)
+            assert err.max() <= tol_fp32(r * L), (name, inv, float(err.max()))
+        return
     if d["role"] == 0:      # one-pass rows
         n, batch, sched = L, (1 << 22) // L + 3, f"single={name}"
     elif d["role"] == 1:    # first pass of a split
@@ -551,7 +562,10 @@ ROWCOL_2D = [((4096, 4096), 1, "rowcol=4"), ((4096, 4096), 1, "rowcol=4;col=c102
              ((1024, 1024), 2, "rowcol=4"), ((64, 256), 3, "rowcol=4"), ((8, 512), 2, "rowcol=4"),
              ((256, 2048), 2, "rowcol=4;xcd=10"), ((2048, 4096), 1, "rowcol=4;col=c512p16w16q_c64"),
              ((16, 1024), 5, "rowcol=4"), ((4096, 4096), 1, "rowcol=4;row=f4096p32w4qx_c64"),
-             ((1024, 4096), 2, "rowcol=2"), ((64, 2048), 3, "rowcol=2;xcd=11")]
+             ((1024, 4096), 2, "rowcol=2"), ((64, 2048), 3, "rowcol=2;xcd=11"),
+             # stage twiddles from two factor tables of W_4096, one-round exchanges
+             ((4096, 4096), 1, "rowcol=4;row=f4096p16w4q_c64;col=c1024p32w16x_c64"),
+             ((16, 4096), 3, "rowcol=4;row=f4096p32w4q_c64")]
 
 
 @pytest.mark.parametrize("shape,batch,sched", ROWCOL_2D)
