@@ -110,7 +110,7 @@ def parse_args(argv=None):
     ap.add_argument("--profile-workload", choices=["step", "image2d", "many", "dft256"], default="step",
                     help="profile mode: the benchmarked step, the 4096x4096 2-D image forward "
                          "transform (tuned schedule, four rotating buffers), the 512 uneven "
-                         "complex64 transforms in one persistent launch (tuned schedule, rotating "
+                         "complex64 transforms in one exec (tuned schedule: two launches, rotating "
                          "buffers of >= 1 GiB), or 65536 x 256 complex64 forward under each "
                          "one-kernel 256-point method (LDS butterflies, matrix cores, cross-lane)")
     return ap.parse_args(argv)
@@ -442,7 +442,7 @@ def configs_report(capi, torch, reps):
     grouped = [(c, n) for n, c in sorted(counts.items())]
     for dt, name in ((C64, "complex64"), (capi.FFT_C16F, "fp16 pairs"), (capi.FFT_C16BF, "bf16 pairs")):
         h = capi.fft_plan_many_ex(sizes, dt, capi.FFT_FORWARD, autotune.many_schedule_for(sizes, dt))
-        add(f"512 uneven 2^8..2^16 in one persistent launch, {name}", [(h, sum(sizes) * (8 if dt == C64 else 4))],
+        add(f"512 uneven 2^8..2^16 in one exec (persistent kernel, two launches), {name}", [(h, sum(sizes) * (8 if dt == C64 else 4))],
             8 if dt == C64 else 4,
             vendor=((lambda *xs: [tf.fft(x) for x in xs]), grouped, "fft per length (9 batched calls)")
             if dt == C64 else None)
