@@ -280,11 +280,14 @@ __host__ __device__ constexpr int tw_split_entries(int L) {
 }
 
 // Stage twiddles staged in LDS: the same entries as the global table, with
-// each k-row of R factors padded to R + 2 so that lanes reading different
-// rows with 16-byte loads start on different banks.
+// each k-row of R factors padded to R + 1.  Lanes k of a wave read row k
+// together; with an odd row stride those rows start on different banks (a
+// stride of R + 2 put rows k and k + 16 on the same banks: the first pass of
+// the 2^20 split stalled twice as many cycles on bank conflicts and ran
+// about 1 us slower per launch).
 template <int L, int P> struct TwLds {
   using S = Sched<L, P>;
-  __host__ __device__ static constexpr int rp(int s) { return S::radix(s) >= 4 ? S::radix(s) + 2 : S::radix(s); }
+  __host__ __device__ static constexpr int rp(int s) { return S::radix(s) >= 4 ? S::radix(s) + 1 : S::radix(s); }
   __host__ __device__ static constexpr int off(int s) {
     return s <= 1 ? 0 : off(s - 1) + S::ns(s - 1) * rp(s - 1);
   }
@@ -559,7 +562,7 @@ k_strip(PassArgs a) {
 template <int L, int P, int W, int EX, bool TWID>
 __host__ __device__ constexpr int pipe_lds_entries() {
   return (EX == 0 ? W * LdsLayout<L>::LS : (W * LdsLayout<L>::LS + 1) / 2) + TwLds<L, P>::SIZE +
-         (TWID ? W * Sched<L, P>::PP : 0);
+         (TWID ? W * (Sched<L, P>::PP + 2) : 0);
 }
 
 template <int L, int P, int W, int LOADM, int STOREM, bool TWID, int EX, typename TS, int DEPTH>
@@ -657,7 +660,9 @@ k_pipe(PassArgs a) {
 #pragma unroll
       for (int j = 0; j < KR; ++j) {
         const int e = tid + j * NT;
-        if (W * PP == KR * NT || e < W * PP) rowl[e] = n.row[j];
+        // rows of PP + 2 entries: the lines of a wave read their step rows
+        // on different banks
+        if (W * PP == KR * NT || e < W * PP) rowl[(e / PP) * (PP + 2) + e % PP] = n.row[j];
       }
       tw_base = cmul(n.hi, n.lo);
     }
@@ -689,7 +694,7 @@ k_pipe(PassArgs a) {
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
       float2 y = v[q];
-      if (TWID) y = cmul(y, cmul(tw_base, rowl[m * PP + q]));
+      if (TWID) y = cmul(y, cmul(tw_base, rowl[m * (PP + 2) + q]));
       y = cscale(y, a.scale);
       y.y = __uint_as_float(__float_as_uint(y.y) ^ sgn_out);
       store_c(dst + q * step, y);
