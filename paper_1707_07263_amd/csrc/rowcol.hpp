@@ -13,10 +13,12 @@
 // row, so each store instruction writes one contiguous run of a row.  (Row
 // outputs interleaved across lanes, W per DPP quad, would skip that LDS
 // round trip, but then each store writes W separate 128 B pieces; measured
-// 86 against 66 us for the 4096-point rows of a 4096^2 image.)  What is left are M-point column transforms over rows W*n1 + k2
-// (stride W rows) for each k2, in place, with output frequency k1 landing
-// on row W*k1 + k2: a column pass of M-point lines whose tiles can be W times
-// wider than those of an R-point column pass for the same LDS.
+// 86 against 66 us for the 4096-point rows of a 4096^2 image.)
+//
+// What is left are M-point column transforms over rows W*n1 + k2 (stride W
+// rows) for each k2, in place, with output frequency k1 landing on row
+// W*k1 + k2: a column pass of M-point lines whose tiles can be W times wider
+// than those of an R-point column pass for the same LDS.
 #pragma once
 
 #include "fft_device.hpp"
@@ -35,8 +37,8 @@ __host__ __device__ constexpr int rowcol_lds_entries() {
 // R / W (a power of two, tw_shift = log2 M), in_line = out_line = C,
 // in_elem = out_elem = 1, in_batch = out_batch = R * C, tw = the row length's
 // stage table (TWP 1) or the factor tables of W_L (TWP 2), tw_lo = W_R^e
-// for e < R.  Persistent: workgroup g walks tiles
-// g, g + G, ... with the next tile's loads in flight.
+// for e < R.  Persistent: workgroup g walks tiles g, g + G, ... with the
+// next tile's loads in flight.
 template <int L, int P, int W, int EX, int TWP, typename TS>
 __global__ void __launch_bounds__((W * Sched<L, P>::T), 1) k_rowcol(PassArgs a) {
   using S = Sched<L, P>;
