@@ -188,6 +188,13 @@ int fft_plan_many(const int64_t *sizes, int64_t count, int dtype, int direction,
  *                      i-th two-pass transform follow the first-pass items of
  *                      the (i+k)-th, so its intermediate is read back while it
  *                      is still in the last-level cache
+ *   'ntst=' 0|1        pipe=2 only: 1 stores every item's results with the
+ *                      nontemporal hint (default 0)
+ *   'ntail=' k         pipe=2 only: the last k items of each launch store
+ *                      with the nontemporal hint, so that less written data
+ *                      is still dirty in the caches when the launch ends and
+ *                      has to be written back before the next launch starts
+ *                      (default 0)
  * FFT_ERR_INVALID_ARGUMENT for a malformed item or an uncompiled combination.
  * In-place exec (in == out) is refused with FFT_ERR_INPLACE when any length
  * uses two passes.

@@ -326,6 +326,13 @@ def tune_many(sizes, dtype=capi.FFT_C64, reps=10, verbose=False):
                 best = (us, f"{base};lag={lag}")
     if best is not None:
         best = _tune_per_length(sizes, best, timed)
+    if best is not None and "pipe=2" in best[1]:
+        # nontemporal stores for the last items of each launch
+        base = best[1]
+        for k in (64, 128, 256, 400):
+            us = timed(f"{base};ntail={k}")
+            if us is not None and us < best[0] * 0.995:
+                best = (us, f"{base};ntail={k}")
     return best[1], [best[0]]
 
 

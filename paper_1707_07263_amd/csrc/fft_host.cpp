@@ -889,7 +889,11 @@ struct ManyOptions {
   // and log2 of the first-pass length N1 of a two-pass transform (0 = the
   // default, ceil(L/2) capped at the longest tile)
   int passes_for[FFT_MAX_LOG2_1D + 1] = {};
-  int nt_store = 0;  // two-launch kernel: stores with the nontemporal hint
+  // two-launch kernel: stores with the nontemporal hint for every item, or
+  // for the last `nt_tail` items of each launch (what is still dirty in the
+  // caches when a launch ends is written back before the next one starts)
+  int nt_store = 0;
+  int nt_tail = 0;
   int lg1_for[FFT_MAX_LOG2_1D + 1] = {};
 };
 
@@ -945,6 +949,9 @@ int parse_many_schedule(const char* s, ManyOptions* o) {
     } else if (key == "ntst") {
       if (v != 0 && v != 1) return FFT_ERR_INVALID_ARGUMENT;
       o->nt_store = (int)v;
+    } else if (key == "ntail") {
+      if (v < 0 || v > (1 << 24)) return FFT_ERR_INVALID_ARGUMENT;
+      o->nt_tail = (int)v;
     } else if (key == "lag") {
       if (v < 0 || v > (1 << 24)) return FFT_ERR_INVALID_ARGUMENT;
       o->lag = (int)v;
@@ -1849,6 +1856,7 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
   if (!rc && opt.pipe == 2) {
     // one self-contained record per item, grouped by queue
     std::vector<ManyItemX> itx(items.size());
+    size_t launch = 0;
     for (size_t i = 0; i < items.size(); ++i) {
       const ManyItem& it = items[i];
       ManyItemX& d = itx[i];
@@ -1857,6 +1865,8 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
       d.lg = it.lg;
       d.a = it.a;
       d.b = it.b;
+      while (launch + 2 < mb.q_off.size() && i >= (size_t)mb.q_off[launch + 1]) ++launch;
+      d.nt = opt.nt_store || (int64_t)i >= (int64_t)mb.q_off[launch + 1] - opt.nt_tail;
       if (it.kind != MANY_SINGLE) {
         const ManyXform& x = xf[it.a];
         d.off = x.off;
@@ -1943,7 +1953,6 @@ int fft_plan_many_ex(const int64_t* sizes, int64_t count, int dtype, int directi
   a.q_off = mp.d_q_off;
   a.phase = 0;
   a.n_phase2 = opt.pipe == 2 ? mb.q_off[2] - mb.q_off[1] : 0;
-  a.nt_store = opt.nt_store;
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
   if (e != hipSuccess) {

@@ -795,7 +795,7 @@ __device__ __forceinline__ void xcompute(const ManyArgs& a, const ManyItemX& d, 
 
 // Stores of an item whose outputs xcompute left in v.  `base` is the lane's
 // line offset for one-pass items.
-template <int L, int P, int NT, typename TS, bool NTST>
+template <int L, int P, int NT, typename TS>
 __device__ __forceinline__ void xstore(const ManyArgs& a, const ManyItemX& d, const float2* v, int64_t base,
                                        int tid) {
   using S = Sched<L, P>;
@@ -824,7 +824,7 @@ __device__ __forceinline__ void xstore(const ManyArgs& a, const ManyItemX& d, co
     }
   }
   if (ok) {
-    if constexpr (NTST) {
+    if (d.nt) {
 #pragma unroll
       for (int q = 0; q < PP; ++q) store_nt(dst + obase + (int64_t)(t + q * T) * oelem, v[q]);
     } else {
@@ -886,7 +886,7 @@ __device__ __forceinline__ int64_t xbase(const ManyArgs& a, const ManyItemX& d, 
 // iteration earlier: the pipelining does not depend on the compiler
 // computing exact wait counts across the many item paths.
 // Launch `a.phase` runs the items q_off[phase] .. q_off[phase+1]-1.
-template <typename TS, int P, int NT, int MAXLG, bool NTST>
+template <typename TS, int P, int NT, int MAXLG>
 __global__ void __launch_bounds__(NT, 512 / NT) k_many_2l(ManyArgs a) {
   static_assert(NT * P >= (1 << MAXLG) && MAXLG <= 12, "tile lengths 2 .. 2^12");
   constexpr int XN = many_lds_max<P, NT, MAXLG>();
@@ -910,6 +910,12 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_many_2l(ManyArgs a) {
   // last in line); later claims come spread over the launch.  Claim k
   // (0-based) then names item 2G + k.
   const int G = (int)gridDim.x;
+  // The first claim goes out before anything else: a claim issued behind
+  // this workgroup's first loads can reach the queue head after other
+  // workgroups' second claims, and then some get four items of a launch
+  // whose items would go three to every workgroup.
+  int claim = kNoClaim;  // thread 0: raw value of the claim in flight
+  if (tid == 0) claim = atomicAdd(head, 1);
   int c = min(lo + (int)blockIdx.x, hi);
   int n = min(lo + G + (int)blockIdx.x, hi);
   ManyItemX dc = xitem(a, c, hi);
@@ -933,8 +939,6 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_many_2l(ManyArgs a) {
     if (tid + k * NT < img) twl[tid + k * NT] = tmp[k];
   // (the barrier at the top of the first iteration makes them visible)
   if (n < hi && dn.kind == MANY_SINGLE) base_n = xbase<P>(a, dn, tid);
-  int claim = kNoClaim;  // thread 0: raw value of the claim in flight
-  if (tid == 0) claim = atomicAdd(head, 1);
 
   float2 v[P];
   ManyItemX dp{};
@@ -948,7 +952,7 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_many_2l(ManyArgs a) {
     vm_wait<0>();
     // stores of the previous item
     if (dp.kind >= 0) {
-      MANY_XCD_SWITCH(dp.lg, (xstore<L, P, NT, TS, NTST>(a, dp, v, base_p, tid)));
+      MANY_XCD_SWITCH(dp.lg, (xstore<L, P, NT, TS>(a, dp, v, base_p, tid)));
     }
 #pragma unroll
     for (int k = 0; k < P; ++k) v[k] = pre.v[k];
@@ -993,7 +997,7 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_many_2l(ManyArgs a) {
   }
   // the last item's stores
   if (dp.kind >= 0) {
-    MANY_XCD_SWITCH(dp.lg, (xstore<L, P, NT, TS, NTST>(a, dp, v, base_p, tid)));
+    MANY_XCD_SWITCH(dp.lg, (xstore<L, P, NT, TS>(a, dp, v, base_p, tid)));
   }
   // The last workgroup out resets this launch's queue head for the next exec.
   __syncthreads();
@@ -1016,10 +1020,7 @@ hipError_t launch_many_2l(const ManyArgs& a, int grid, hipStream_t s) {
     ManyArgs b = a;
     b.phase = ph;
     if (ph == 1 && a.n_phase2 == 0) break;
-    if (a.nt_store)
-      hipLaunchKernelGGL((k_many_2l<TS, P, NT, MAXLG, true>), dim3(grid), dim3(NT), 0, s, b);
-    else
-      hipLaunchKernelGGL((k_many_2l<TS, P, NT, MAXLG, false>), dim3(grid), dim3(NT), 0, s, b);
+    hipLaunchKernelGGL((k_many_2l<TS, P, NT, MAXLG>), dim3(grid), dim3(NT), 0, s, b);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1029,11 +1030,8 @@ hipError_t launch_many_2l(const ManyArgs& a, int grid, hipStream_t s) {
 template <typename TS, int P, int NT, int MAXLG>
 int blocks_many_2l() {
   int n = 0;
-  int n2 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_many_2l<TS, P, NT, MAXLG, false>, NT, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n2, k_many_2l<TS, P, NT, MAXLG, true>, NT, 0) != hipSuccess)
-    return 0;
-  return n < n2 ? n : n2;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_many_2l<TS, P, NT, MAXLG>, NT, 0) != hipSuccess) return 0;
+  return n;
 }
 
 template <typename TS, int P, int NT, int MAXLG>

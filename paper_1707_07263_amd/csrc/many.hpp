@@ -49,7 +49,8 @@ struct ManyItemX {
   int64_t tw_lo;     // first pass: W_N^j tables (lo at tw_lo, hi at tw_lo + N1)
   int64_t tw_step;   // first pass: step rows W_N^{n2*q*(N1/P)}
   int32_t lg1, lgN;  // log2 N1 and log2 N (first/second pass)
-  int32_t pad[4];
+  int32_t nt;        // stores with the nontemporal hint
+  int32_t pad[3];
 };
 static_assert(sizeof(ManyItemX) == 64, "one 64-byte record per item");
 
@@ -81,7 +82,6 @@ struct ManyArgs {
   const ManyItemX* itx;
   const int32_t* q_off;
   int32_t phase, n_phase2;
-  int32_t nt_store;   // two-launch kernel: stores with the nontemporal hint
   int32_t tw_img_len_ph[2];  // two-launch kernel: image entries each launch's lengths need
   int32_t* watchdog;  // flag set when a bounded wait expires
 };

@@ -116,7 +116,7 @@ def test_uneven_512_16bit(dev, dt, pipe):
                                       "pipe=2;threads=512;pass2=1", "pipe=2;threads=512;pass2=9",
                                       "pipe=2;threads=512;pass.11=2;pass.12=2;n1.16=6;n1.15=9;n1.14=7",
                                       "pipe=2;threads=256", "pipe=2;threads=256;ntst=1;pass2=9",
-                                      "pipe=2;threads=512;ntst=1",
+                                      "pipe=2;threads=512;ntst=1", "pipe=2;threads=512;ntail=40",
                                       "pipe=0;threads=512;n1.16=10;pass.9=2;n1.5=2"])
 def test_many_schedules_and_small_sizes(dev, schedule):
     # every length 2^0..2^16 twice, shuffled, under each compiled schedule
@@ -264,7 +264,7 @@ def test_many_errors(dev):
 
 
 @pytest.mark.parametrize("schedule", ["pipe=2;threads=512", "pipe=2;threads=512;pass2=9",
-                                      "pipe=2;threads=256;ntst=1"])
+                                      "pipe=2;threads=256;ntst=1", "pipe=2;threads=512;ntail=300"])
 def test_many_two_launch_repeat_inverse_inplace(dev, schedule):
     # two launches per exec: repeated execs of one plan agree bitwise (each
     # launch resets its own queue head), the inverse with the default and a
