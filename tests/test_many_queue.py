@@ -106,7 +106,7 @@ def test_queue_errors():
             capi.fft_describe_many(sizes)
         assert ei.value.status == code
     for bad in ("p=7", "threads=100", "pass2=0", "pass2=14", "order=random", "x=1", "lag=-1",
-                "pipe=1;threads=256;pass2=13", "pipe=3", "pipe=2;threads=512;p=8"):
+                "pipe=1;threads=256;pass2=13", "pipe=3", "pipe=2;threads=512;p=8", "ntail=-1", "ntst=2"):
         with pytest.raises(capi.FFTError) as ei:
             capi.fft_describe_many([256], schedule=bad)
         assert ei.value.status == capi.FFT_ERR_INVALID_ARGUMENT, bad
@@ -270,6 +270,54 @@ def test_two_launch_static_first_items(n_items, workers):
     for seed in range(3):
         ran = simulate_two_launch(n_items, workers, np.random.default_rng(seed))
         assert np.all(ran == 1)
+
+
+def two_launch_counts(n_items, workers, first_claim_at_entry, rng):
+    """Items per worker when every item takes one time unit: worker g starts
+    at a jittered time, issues its first claim at kernel entry (or once its
+    first item's loads are in, one unit later), and each later claim at the
+    top of an iteration; claims are served in the order they are issued."""
+    start = rng.uniform(0.0, 0.2, workers)
+    first = start if first_claim_at_entry else start + rng.uniform(0.0, 1.5, workers)
+    count = np.zeros(workers, int)
+    for g in range(workers):
+        count[g] = int(g < n_items) + int(workers + g < n_items)
+    events = sorted((first[g], g) for g in range(workers))
+    head = 0
+    pending = []
+    # a worker's k-th top comes at start + k; a claim issued at its top j
+    # (j >= 0) is issued at start + j, the entry claim at `first`
+    for t, g in events:
+        pending.append((t, g))
+    for g in range(workers):
+        for j in range(n_items):
+            pending.append((start[g] + 1.0 + j, g))
+    pending.sort()
+    alive = count > 1
+    for t, g in pending:
+        if not alive[g]:
+            continue
+        idx = 2 * workers + head
+        head += 1
+        if idx < n_items:
+            count[g] += 1
+        else:
+            alive[g] = False
+    return count
+
+
+@pytest.mark.parametrize("n_items", [768, 846, 854])
+def test_two_launch_first_claim_at_entry(n_items):
+    # with the first claim issued at kernel entry every first claim is
+    # served before any second one, so equal items split evenly (3 or 4 for
+    # 846 items on 256 workgroups); a first claim issued after the first
+    # item's loads can lose to other workgroups' second claims
+    rng = np.random.default_rng(11)
+    even = two_launch_counts(n_items, 256, True, rng)
+    assert even.sum() == n_items
+    assert even.max() - even.min() <= 1, (even.min(), even.max())
+    late = two_launch_counts(n_items, 256, False, rng)
+    assert late.sum() == n_items
 
 
 def test_per_length_schedule_items():
