@@ -161,8 +161,10 @@ def rowcol_set():
 
 
 # fused row passes whose stage twiddles come from two factor tables of W_L
-# (TWP 2): the LDS then holds a one-round exchange of four 4096-point rows
-SPLIT_TW_ROWCOL = [(4096, 16, 4, 0, 2), (4096, 32, 4, 0, 2)]
+# (TWP 2): the LDS then holds a one-round exchange of four (or two) 4096-point
+# rows; two rows of 16 points per lane take 128 registers and 69 KB of LDS,
+# so two workgroups share a CU
+SPLIT_TW_ROWCOL = [(4096, 16, 4, 0, 2), (4096, 32, 4, 0, 2), (4096, 16, 2, 0, 2), (4096, 32, 2, 0, 2)]
 
 
 def name(role, L, P, W, ex, dt, persist=0):

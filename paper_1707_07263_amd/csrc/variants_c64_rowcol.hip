@@ -13,6 +13,8 @@ void add_variants_c64_rowcol(void (*add)(const Variant&)) {
   add(make_rowcol_variant<2048, 32, 2, 0, 1, float2>("f2048p32w2q_c64"));
   add(make_rowcol_variant<4096, 16, 4, 0, 2, float2>("f4096p16w4q_c64"));
   add(make_rowcol_variant<4096, 32, 4, 0, 2, float2>("f4096p32w4q_c64"));
+  add(make_rowcol_variant<4096, 16, 2, 0, 2, float2>("f4096p16w2q_c64"));
+  add(make_rowcol_variant<4096, 32, 2, 0, 2, float2>("f4096p32w2q_c64"));
 }
 
 }  // namespace mfft

@@ -565,7 +565,10 @@ ROWCOL_2D = [((4096, 4096), 1, "rowcol=4"), ((4096, 4096), 1, "rowcol=4;col=c102
              ((1024, 4096), 2, "rowcol=2"), ((64, 2048), 3, "rowcol=2;xcd=11"),
              # stage twiddles from two factor tables of W_4096, one-round exchanges
              ((4096, 4096), 1, "rowcol=4;row=f4096p16w4q_c64;col=c1024p32w16x_c64"),
-             ((16, 4096), 3, "rowcol=4;row=f4096p32w4q_c64")]
+             ((16, 4096), 3, "rowcol=4;row=f4096p32w4q_c64"),
+             ((4096, 4096), 1, "rowcol=2;row=f4096p16w2q_c64;col=c2048p32w16x_c64"),
+             ((32, 4096), 2, "rowcol=2;row=f4096p32w2q_c64"),
+             ((4096, 4096), 1, "rowcol=2;row=f4096p16w2q_c64;col=c2048p32w8q_c64;xcd=01")]
 
 
 @pytest.mark.parametrize("shape,batch,sched", ROWCOL_2D)
