@@ -184,18 +184,19 @@ __device__ __forceinline__ void store_c(float2* p, float2 v) { *p = v; }
 __device__ __forceinline__ void store_c(__half2* p, float2 v) {
   *p = __halves2half2(__float2half_rn(v.x), __float2half_rn(v.y));
 }
-// float32 -> bfloat16, round to nearest, ties to even (NaN stays NaN).
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// Two float32 values -> a packed bfloat16 pair (lo in the low half), round
+// to nearest, ties to even; NaN stays NaN.  gfx950 converts the pair in one
+// vector instruction (the conversion written out with integer operations
+// took about a dozen per pair).
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  bf16x2 r;
+  r.x = (__bf16)lo;
+  r.y = (__bf16)hi;
+  return __builtin_bit_cast(uint32_t, r);
 }
 __device__ __forceinline__ void store_c(c16bf* p, float2 v) {
-  c16bf o;
-  o.x = f32_to_bf16(v.x);
-  o.y = f32_to_bf16(v.y);
-  *p = o;
+  *reinterpret_cast<uint32_t*>(p) = pack_bf16x2(v.x, v.y);
 }
 
 // ---------------------------------------------------------------------------

@@ -735,7 +735,7 @@ __device__ __forceinline__ void store_nt(__half2* p, float2 v) {
   __builtin_nontemporal_store(*reinterpret_cast<const uint32_t*>(&h), reinterpret_cast<uint32_t*>(p));
 }
 __device__ __forceinline__ void store_nt(c16bf* p, float2 v) {
-  const uint32_t w = (uint32_t)f32_to_bf16(v.x) | ((uint32_t)f32_to_bf16(v.y) << 16);
+  const uint32_t w = pack_bf16x2(v.x, v.y);
   __builtin_nontemporal_store(w, reinterpret_cast<uint32_t*>(p));
 }
 

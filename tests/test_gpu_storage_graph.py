@@ -76,6 +76,32 @@ def test_16bit_three_pass_2d(dev, tname, shape):
     assert err.max() <= TOL16[tname], float(err.max())
 
 
+def test_bf16_store_rounds_half_to_even(dev):
+    # 2-point transforms X0 = x0 + x1, X1 = x0 - x1 of bf16 inputs: for these
+    # pairs both are exact in FP32, so the only rounding is the store to
+    # bf16, which must match torch's CPU conversion (nearest, ties to even)
+    # bit for bit, halfway cases included
+    u = 2.0 ** -8
+    pairs = [(1.0, u),                 # 1 + 2^-8: halfway, to 1 (even)
+             (1.0 + 2 * u, u),         # 1 + 3 2^-8: halfway, to 1 + 2^-6 (even)
+             (1.0, 0.75 * u),          # below halfway: to 1
+             (1.0, 1.5 * u),           # above halfway: to 1 + 2^-7
+             (-1.0, -u),               # negative halfway
+             (3.0, 3 * u),             # halfway at a larger exponent
+             (0.5, 2.0 ** -9 + 2.0 ** -16), (1.5, -u), (0.0, 0.0), (-2.0, 3 * u)]
+    x = np.array([[a + 1j * b, b - 1j * a] for a, b in pairs])  # rows: (x0, x1)
+    xt = to_gpu_16(x, dev, torch.bfloat16)
+    assert np.array_equal(from_gpu_16(xt), x)  # the inputs are bf16 values
+    y = from_gpu_16(api.fft(xt))
+    torch.cuda.synchronize()
+    s32 = np.stack([x[:, 0] + x[:, 1], x[:, 0] - x[:, 1]], axis=1)
+    pair = np.stack([s32.real, s32.imag], axis=-1)
+    assert np.array_equal(pair.astype(np.float32).astype(np.float64), pair)  # exact in FP32
+    ref = torch.from_numpy(pair.astype(np.float32)).to(torch.bfloat16).float().numpy().astype(np.float64)
+    assert np.array_equal(y, ref[..., 0] + 1j * ref[..., 1])
+    assert y[0, 0].real == 1.0 and y[1, 0].real == 1.0 + 2.0 ** -6
+
+
 def test_wrappers_match_capi(dev):
     x = workloads.normal_batch(4096, 5, seed=61).astype(np.complex64)
     xt = to_gpu_c64(x, dev)
