@@ -181,8 +181,18 @@ __device__ __forceinline__ float2 load_stream(const float2* p) {
   return make_float2(r.x, r.y);
 }
 __device__ __forceinline__ void store_c(float2* p, float2 v) { *p = v; }
+// Two float32 values -> a packed float16 pair (lo in the low half), round
+// to nearest, ties to even (the default rounding mode): one vector
+// instruction on gfx950, where converting each half and packing takes three.
+__device__ __forceinline__ uint32_t pack_f16x2(float lo, float hi) {
+  typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+  f16x2 r;
+  r.x = (_Float16)lo;
+  r.y = (_Float16)hi;
+  return __builtin_bit_cast(uint32_t, r);
+}
 __device__ __forceinline__ void store_c(__half2* p, float2 v) {
-  *p = __halves2half2(__float2half_rn(v.x), __float2half_rn(v.y));
+  *reinterpret_cast<uint32_t*>(p) = pack_f16x2(v.x, v.y);
 }
 // Two float32 values -> a packed bfloat16 pair (lo in the low half), round
 // to nearest, ties to even; NaN stays NaN.  gfx950 converts the pair in one

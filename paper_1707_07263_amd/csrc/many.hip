@@ -731,8 +731,7 @@ __device__ __forceinline__ void store_nt(float2* p, float2 v) {
   __builtin_nontemporal_store(r, reinterpret_cast<f2v*>(p));
 }
 __device__ __forceinline__ void store_nt(__half2* p, float2 v) {
-  const __half2 h = __halves2half2(__float2half_rn(v.x), __float2half_rn(v.y));
-  __builtin_nontemporal_store(*reinterpret_cast<const uint32_t*>(&h), reinterpret_cast<uint32_t*>(p));
+  __builtin_nontemporal_store(pack_f16x2(v.x, v.y), reinterpret_cast<uint32_t*>(p));
 }
 __device__ __forceinline__ void store_nt(c16bf* p, float2 v) {
   const uint32_t w = pack_bf16x2(v.x, v.y);

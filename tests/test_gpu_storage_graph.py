@@ -102,6 +102,25 @@ def test_bf16_store_rounds_half_to_even(dev):
     assert y[0, 0].real == 1.0 and y[1, 0].real == 1.0 + 2.0 ** -6
 
 
+def test_f16_store_rounds_half_to_even(dev):
+    # as above for float16 (10 fraction bits): ties at 1 + 2^-11 and
+    # 1 + 3 2^-11, both signs, and one overflow-free large value
+    u = 2.0 ** -11
+    pairs = [(1.0, u), (1.0 + 2 * u, u), (1.0, 0.75 * u), (1.0, 1.5 * u), (-1.0, -u),
+             (1024.0, 0.5), (1024.0, 1.5), (0.0, 0.0), (-2.0, 3 * u), (0.25, 2.0 ** -14)]
+    x = np.array([[a + 1j * b, b - 1j * a] for a, b in pairs])
+    xt = to_gpu_16(x, dev, torch.float16)
+    assert np.array_equal(from_gpu_16(xt), x)
+    y = from_gpu_16(api.fft(xt))
+    torch.cuda.synchronize()
+    s32 = np.stack([x[:, 0] + x[:, 1], x[:, 0] - x[:, 1]], axis=1)
+    pair = np.stack([s32.real, s32.imag], axis=-1)
+    assert np.array_equal(pair.astype(np.float32).astype(np.float64), pair)
+    ref = pair.astype(np.float16).astype(np.float64)  # numpy: nearest, ties to even
+    assert np.array_equal(y, ref[..., 0] + 1j * ref[..., 1])
+    assert y[0, 0].real == 1.0 and y[1, 0].real == 1.0 + 2.0 ** -9 and y[5, 0].real == 1024.0
+
+
 def test_wrappers_match_capi(dev):
     x = workloads.normal_batch(4096, 5, seed=61).astype(np.complex64)
     xt = to_gpu_c64(x, dev)
