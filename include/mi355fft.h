@@ -108,6 +108,12 @@ int fft_plan(const int64_t *n, int64_t batch, int dims, int dtype, int direction
  *             | 'col3=' 0|1           (2-D: columns as two sub-passes of sqrt(rows)
  *                                       points; rows a power of 4, at least 2 columns)
  *             | 'colt=' variant       (the first of those sub-passes)
+ *             | 'blk=' 0|8|16|32      (2-D two-pass plan: the row pass writes its
+ *                                       output in blocks of that many columns,
+ *                                       each block's rows back to back, so that
+ *                                       a column tile reads one contiguous run;
+ *                                       the column pass writes the natural
+ *                                       layout.  0, the default: natural order)
  *             | 'rowcol=' 0|2|4       (2-D, complex64: the row pass also takes the
  *                                       first radix-r step of the columns (R =
  *                                       r*M, eq. 5): a tile holds rows n1 + M*j,
@@ -146,11 +152,15 @@ int fft_plan_ex(const int64_t *n, int64_t batch, int dims, int dtype, int direct
  * Plan `count` independent 1-D transforms whose lengths sizes[0..count) are
  * powers of two in 1 .. 2^24, packed back to back in the given order (the
  * offset of transform i is the sum of sizes[0..i)).  fft_exec runs them all
- * in ONE persistent kernel launch that takes work items from a device queue;
- * a second-pass item of a two-pass transform waits on that transform's
- * completion counter.  The queue state lives in the plan's workspace and is
- * reset by the kernel itself, so the launch can be captured in a hipGraph
- * and replayed.  Two fft_exec calls that share one workspace must not run
+ * with one persistent kernel.  By default ('pipe=2' below) it is launched
+ * twice per exec: the first launch runs every one-pass transform and the
+ * first pass of every two-pass one, the second launch every second pass, so
+ * the kernel boundary orders each transform's passes (Sec. 2.3.3); inside a
+ * launch the workgroups claim work items from a device queue and never wait
+ * for one another.  The single-launch kernels ('pipe=0|1') chain a
+ * transform's passes by a completion counter instead.  The queue state lives
+ * in the plan's workspace and is reset by the kernel itself, so the launches
+ * can be captured in a hipGraph and replayed.  Two fft_exec calls that share one workspace must not run
  * concurrently.
  */
 int fft_plan_many(const int64_t *sizes, int64_t count, int dtype, int direction,
