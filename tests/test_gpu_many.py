@@ -78,7 +78,7 @@ def test_uneven_512_complex64(dev, which):
 
 
 @pytest.mark.parametrize("pipe", [None, "pipe=1;threads=512", "pipe=1;threads=256", "pipe=2;threads=512",
-                                  "pipe=2;threads=256;ntst=1"])
+                                  "pipe=2;threads=256;ntst=1", "pipe=2;threads=512;ntail=200"])
 @pytest.mark.parametrize("dt", ["f16", "bf16"])
 def test_uneven_512_16bit(dev, dt, pipe):
     code, tname = DT16[dt]
